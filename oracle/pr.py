@@ -1,0 +1,106 @@
+"""FP64 phase-retrieval oracle (test infrastructure only).
+
+Section V of Gao & Cao: free-space propagation by the angular spectrum method
+(Eq. 23), the amplitude data-fidelity term F of Eq. (24) summed over several
+propagation distances, its gradient (Eq. 27), and FISTA (Algorithm 1) with the
+constrained-TV denoiser of ``oracle.tv`` as the proximity operator (Eq. 15 with
+lam = tau * gamma).
+
+Readings where the paper is silent:
+  * frequencies f_x, f_y are numpy.fft.fftfreq(n, pixel) / (m, pixel) in the
+    unshifted FFT order; evanescent frequencies (negative radicand) get H = 0;
+  * F^{-1} is the exact inverse of F, so A_d is unitary on the propagating band;
+  * z / |z| at z = 0 is taken as 1 (Appendix C allows any unit phasor there);
+  * with several distances, F = sum_d F_d;
+  * Algorithm 1's gradient point is z_k, and x_{k-1} at k = 1 is x_0;
+  * gamma is fixed (the paper's line search is not specified).
+
+Parity status: ``transfer``, ``A``, ``AH``, ``data_term`` and ``grad_F`` are
+pinned by closed forms and finite differences; ``fista``'s end-to-end iterates
+are parity unpinned (the paper prints no values).
+"""
+import numpy as np
+
+from . import tv as _tv
+
+
+def transfer(m, n, distance, wavelength, pixel):
+    """H_d(f_x, f_y) = exp(i 2 pi d / lambda_s sqrt(1 - (lambda_s f_x)^2 - (lambda_s f_y)^2))."""
+    fx = np.fft.fftfreq(n, d=pixel)[None, :]
+    fy = np.fft.fftfreq(m, d=pixel)[:, None]
+    arg = 1.0 - (wavelength * fx) ** 2 - (wavelength * fy) ** 2
+    prop = arg > 0
+    phase = 2.0 * np.pi / wavelength * distance * np.sqrt(np.where(prop, arg, 0.0))
+    return np.where(prop, np.exp(1j * phase), 0.0)
+
+
+def A(x, H):
+    """Forward propagation, Eq. (23)."""
+    return np.fft.ifft2(np.fft.fft2(x) * H)
+
+
+def AH(z, H):
+    """Adjoint of A: F^{-1}{ conj(H) F[z] } (F unitary up to the ifft scale)."""
+    return np.fft.ifft2(np.fft.fft2(z) * np.conj(H))
+
+
+def _phasor(z):
+    a = np.abs(z)
+    return np.where(a > 0, z / np.where(a > 0, a, 1.0), 1.0 + 0j), a
+
+
+def data_term(x, sqrt_y, Hs):
+    """F(x) = sum_d 0.5 || |A_d x| - sqrt(y_d) ||_F^2 (Eq. 24)."""
+    return float(sum(0.5 * np.sum((np.abs(A(x, H)) - s) ** 2) for s, H in zip(sqrt_y, Hs)))
+
+
+def grad_F(x, sqrt_y, Hs):
+    """Eq. (27) summed over distances; the returned complex array holds the
+    real-pair gradient (dF/du, dF/dv) as real + i imag."""
+    g = np.zeros_like(np.asarray(x, dtype=np.complex128))
+    for s, H in zip(sqrt_y, Hs):
+        z = A(x, H)
+        ph, a = _phasor(z)
+        g = g + AH(ph * (a - s), H)
+    return g
+
+
+def backprop(sqrt_y, Hs):
+    """Directly back-propagated field: (1/D) sum_d A_d^H sqrt(y_d)."""
+    return sum(AH(s.astype(np.complex128), H) for s, H in zip(sqrt_y, Hs)) / len(Hs)
+
+
+def fista(y, distances, wavelength, pixel, outer, inner, tau, gamma,
+          kind="1i", alpha=0.5, constraint="modulus", x0=None, accelerate=True):
+    """Algorithm 1 with prox_{gamma R} = FGP (Algorithm 2) at lam = tau*gamma.
+
+    y: (D, m, n) intensities. Returns (x_K, loss) where loss[k-1] = F(z_k), the
+    data term at the k-th gradient point. accelerate=False gives the plain
+    proximal gradient iteration of Eq. (14) (ISTA).
+    """
+    y = np.asarray(y, dtype=np.float64)
+    D, m, n = y.shape
+    Hs = [transfer(m, n, d, wavelength, pixel) for d in distances]
+    sqrt_y = [np.sqrt(np.maximum(yy, 0.0)) for yy in y]
+    x_prev = backprop(sqrt_y, Hs) if x0 is None else np.asarray(x0, dtype=np.complex128)
+    z = x_prev.copy()
+    t = 1.0
+    lam = tau * gamma
+    loss = []
+    for _ in range(outer):
+        loss.append(data_term(z, sqrt_y, Hs))
+        v = z - gamma * grad_F(z, sqrt_y, Hs)
+        x = _tv.fgp(v, lam, inner, kind, alpha, constraint)
+        t_new = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        beta = (t - 1.0) / t_new if accelerate else 0.0
+        z = x + beta * (x - x_prev)
+        x_prev, t = x, t_new
+    return x_prev, np.array(loss)
+
+
+def phase_rmse(x, truth):
+    """Phase RMSE with the best global phase removed (Section VI-A)."""
+    c = np.vdot(x, truth)
+    rot = c / abs(c) if abs(c) > 0 else 1.0
+    d = np.angle(x * rot * np.conj(truth))
+    return float(np.sqrt(np.mean(d * d)))

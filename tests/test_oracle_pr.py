@@ -1,0 +1,115 @@
+"""Pins for the phase-retrieval oracle: the FFT convention against a naive DFT,
+the angular-spectrum transfer function's closed-form properties, the data-term
+gradient against finite differences and its closed-form special cases, and the
+qualitative behaviour of Algorithm 1."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pr
+
+
+def naive_dft2(x, sign):
+    m, n = x.shape
+    Fm = np.exp(sign * 2j * np.pi * np.outer(np.arange(m), np.arange(m)) / m)
+    Fn = np.exp(sign * 2j * np.pi * np.outer(np.arange(n), np.arange(n)) / n)
+    return Fm @ x @ Fn.T
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (16, 4), (5, 12)])
+def test_fft_convention_matches_naive_dft(shape, rng):
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    np.testing.assert_allclose(np.fft.fft2(x), naive_dft2(x, -1), atol=1e-10)
+    np.testing.assert_allclose(np.fft.ifft2(x), naive_dft2(x, +1) / x.size, atol=1e-12)
+
+
+def test_transfer_function_properties():
+    m, n, lam_s, px = 32, 24, 532e-9, 4e-6
+    H1 = pr.transfer(m, n, 1.0e-3, lam_s, px)
+    H2 = pr.transfer(m, n, 1.5e-3, lam_s, px)
+    H12 = pr.transfer(m, n, 2.5e-3, lam_s, px)
+    np.testing.assert_allclose(np.abs(H1), 1.0, atol=1e-14)        # all propagating here
+    np.testing.assert_allclose(H1 * H2, H12, atol=1e-9)
+    np.testing.assert_allclose(pr.transfer(m, n, 0.0, lam_s, px), 1.0, atol=0)
+    np.testing.assert_allclose(pr.transfer(m, n, -1.0e-3, lam_s, px), np.conj(H1), atol=1e-12)
+    # DC term: phase 2 pi d / lambda exactly
+    assert abs(H1[0, 0] - np.exp(2j * np.pi * 1.0e-3 / lam_s)) < 1e-9
+    # evanescent band is zero when the grid's highest frequency exceeds 1/lambda
+    He = pr.transfer(16, 16, 1e-3, 1.5e-6, 1e-6)
+    fx = np.fft.fftfreq(16, 1e-6)
+    ev = (1.5e-6 * fx[None, :]) ** 2 + (1.5e-6 * fx[:, None]) ** 2 >= 1
+    assert ev.any() and np.all(He[ev] == 0) and np.allclose(np.abs(He[~ev]), 1)
+
+
+def test_propagator_unitary_and_adjoint(rng):
+    m, n = 32, 32
+    H = pr.transfer(m, n, 2e-3, 532e-9, 4e-6)
+    x = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    z = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    assert abs(np.linalg.norm(pr.A(x, H)) - np.linalg.norm(x)) < 1e-10
+    assert abs(np.vdot(z, pr.A(x, H)) - np.vdot(pr.AH(z, H), x)) < 1e-9
+    np.testing.assert_allclose(pr.AH(pr.A(x, H), H), x, atol=1e-12)
+    Hm = pr.transfer(m, n, -2e-3, 532e-9, 4e-6)
+    np.testing.assert_allclose(pr.A(z, Hm), pr.AH(z, H), atol=1e-12)
+
+
+def small_problem(rng, m=32, D=2):
+    truth = synth.config5_object(seed=3, size=m, n_shapes=6, sigma_px=1.5)
+    dists = (1.0e-3, 2.0e-3)[:D]
+    Hs = [pr.transfer(m, m, d, 532e-9, 4e-6) for d in dists]
+    sy = [np.abs(pr.A(truth, H)) for H in Hs]
+    return truth, Hs, sy
+
+
+def test_grad_matches_finite_differences(rng):
+    truth, Hs, sy = small_problem(rng)
+    x = truth * np.exp(0.3j) + 0.05 * (rng.standard_normal(truth.shape) + 1j * rng.standard_normal(truth.shape))
+    g = pr.grad_F(x, sy, Hs)
+    h = 1e-6
+    for _ in range(3):
+        d = rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)
+        fd = (pr.data_term(x + h * d, sy, Hs) - pr.data_term(x - h * d, sy, Hs)) / (2 * h)
+        an = float(np.sum(g.real * d.real + g.imag * d.imag))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+def test_grad_closed_form_cases(rng):
+    truth, Hs, sy = small_problem(rng)
+    # noise-free data: the truth is a stationary point
+    assert np.abs(pr.grad_F(truth, sy, Hs)).max() < 1e-12
+    # global phase: grad(e^{i th} x) = e^{i th} grad(x)
+    x = truth + 0.1
+    th = np.exp(1.1j)
+    np.testing.assert_allclose(pr.grad_F(th * x, sy, Hs), th * pr.grad_F(x, sy, Hs), atol=1e-12)
+    # one distance, unit step: x - grad F(x) = A^H[ sqrt(y) A x / |A x| ] (magnitude replacement)
+    H, s = Hs[0], sy[0]
+    Ax = pr.A(x, H)
+    mr = pr.AH(s * Ax / np.abs(Ax), H)
+    np.testing.assert_allclose(x - pr.grad_F(x, [s], [H]), mr, atol=1e-12)
+
+
+def test_zero_field_uses_unit_phasor():
+    H = pr.transfer(8, 8, 1e-3, 532e-9, 4e-6)
+    s = np.ones((8, 8))
+    g = pr.grad_F(np.zeros((8, 8), complex), [s], [H])
+    np.testing.assert_allclose(g, pr.AH(-np.ones((8, 8)), H), atol=1e-14)
+
+
+def test_fista_reduces_loss_and_phase_error(rng):
+    truth, Hs, sy = small_problem(rng, m=32, D=2)
+    y = np.stack([s ** 2 for s in sy])
+    x0 = pr.backprop(sy, Hs)
+    e0 = pr.phase_rmse(x0, truth)
+    x, loss = pr.fista(y, (1.0e-3, 2.0e-3), 532e-9, 4e-6, outer=30, inner=10, tau=0.002, gamma=0.5)
+    assert loss[-1] < 0.2 * loss[0]
+    assert pr.phase_rmse(x, truth) < e0
+    assert np.all(np.abs(x) <= 1 + 1e-12)
+    # ISTA (no momentum) is slower than FISTA on the same problem (Fig. 5's observation)
+    _, loss_ista = pr.fista(y, (1.0e-3, 2.0e-3), 532e-9, 4e-6, outer=30, inner=10, tau=0.002, gamma=0.5,
+                            accelerate=False)
+    assert loss[-1] < loss_ista[-1]
+
+
+def test_phase_rmse_ignores_global_phase(rng):
+    truth = synth.config5_object(seed=1, size=16, n_shapes=3, sigma_px=1.0)
+    assert pr.phase_rmse(truth * np.exp(2.2j), truth) < 1e-12
