@@ -1,0 +1,215 @@
+/*
+ * ctv.h - C ABI of the MI355X (gfx950) complex constrained total-variation
+ * denoiser and its proximal-gradient phase-retrieval application.
+ *
+ * Method: Gao & Cao, "A Complex Constrained Total Variation Image Denoising
+ * Algorithm with Application to Phase Retrieval" (arXiv 2109.05496).
+ *   problem        min_{x in C} 0.5 ||x - b||_F^2 + lambda ||x||_TV      (Eq. 1)
+ *   TV kinds       type-I / type-II, isotropic / anisotropic             (Eqs. 7-10)
+ *   constraint C   none (C = C^{m x n}) or |x_jk| <= 1                   (Eq. 25, projection Eq. 26)
+ *                  optionally intersected with a 0/1 support mask (x = 0 where the mask is 0)
+ *   solver         fast gradient projection on the dual                  (Algorithm 2, Eqs. 16-20, 33-37)
+ *   output         x = P_C(b - lambda L^T q_K)                           (Eq. 18)
+ *   PR application FISTA (Algorithm 1) with angular-spectrum propagation (Eq. 23),
+ *                  amplitude data term (Eq. 24) and its gradient (Eq. 27).
+ *
+ * Conventions for every entry point
+ *   - Images are complex64, interleaved (re, im) float pairs, row-major
+ *     [batch][m][n]; m = rows (the paper's index j), n = columns (index k).
+ *   - Pointers are DEVICE pointers unless the name ends in _host.
+ *   - The caller owns every buffer. Only *_plan_create allocates device memory
+ *     (and frees it in *_plan_destroy); no other call allocates, so execute
+ *     calls can be captured into a HIP graph.
+ *   - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL = the
+ *     default stream). They return after enqueueing work.
+ *   - Arguments are validated before any device work; on error nothing is
+ *     enqueued and a message is available from ctv_last_error() (thread-local).
+ *   - NaN/Inf inputs are not checked; they propagate.
+ *   - FGP state ("dual state") layout: float[batch][2][m][n][4]. Plane 0 holds
+ *     q_k, plane 1 holds the extrapolated point r_{k+1} of Algorithm 2, line 5.
+ *     Per pixel the four floats are (r1, s1, r2, s2) = (Re Q1, Im Q1, Re Q2,
+ *     Im Q2) with Q1 = r^(1) + i s^(1) (vertical differences) and
+ *     Q2 = r^(2) + i s^(2) (horizontal differences); the entries that do not
+ *     exist in the paper (Q1 on the last row, Q2 on the last column) are 0.
+ */
+#ifndef CTV_H
+#define CTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ctv_status;
+#define CTV_OK 0
+#define CTV_ERR_INVALID_ARG (-1)
+#define CTV_ERR_WORKSPACE (-2)
+#define CTV_ERR_HIP (-3)
+#define CTV_ERR_UNSUPPORTED (-4)
+
+/* TV kinds: type-I isotropic (Eq. 7), type-I anisotropic (Eq. 8),
+ * type-II isotropic (Eq. 9), type-II anisotropic (Eq. 10). */
+#define CTV_TV_1I 0
+#define CTV_TV_1A 1
+#define CTV_TV_2I 2
+#define CTV_TV_2A 3
+
+/* Constraint sets: CTV_C_NONE is C = C^{m x n} (the unconstrained "TV" model of
+ * Section VI-A); CTV_C_MODULUS is Eq. (25), |x_jk| <= 1. */
+#define CTV_C_NONE 0
+#define CTV_C_MODULUS 1
+
+typedef void* ctv_stream_t; /* hipStream_t */
+
+typedef struct {
+  uint32_t struct_size; /* sizeof(ctv_params) */
+  int32_t tv_kind;      /* CTV_TV_* */
+  float alpha;          /* type-II weight in [0, 1] (Eqs. 9-10); ignored for type-I */
+  int32_t constraint;   /* CTV_C_* */
+  int32_t iters;        /* K >= 0, FGP iterations (Algorithm 2) */
+  int32_t fuse;         /* iterations fused per kernel launch, 1..16; 0 = automatic */
+} ctv_params;
+
+/* Library version (major*10000 + minor*100 + patch) and last error message. */
+int32_t ctv_version(void);
+const char* ctv_last_error(void);
+
+/* Workspace (and checkpoint storage) needed by ctv_denoise /
+ * ctv_denoise_backward for `batch` images of m x n.
+ *   ws_bytes    : scratch for ctv_denoise; ctv_denoise_backward needs
+ *                 ctv_backward_workspace_size() instead.
+ *   saved_bytes : size of the `saved` checkpoint buffer for ckpt_every > 0
+ *                 (ceil(K / ckpt_every) dual states), else 0.
+ * Either output pointer may be NULL. */
+ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
+                              int32_t ckpt_every, size_t* ws_bytes, size_t* saved_bytes);
+
+/* ctv_denoise - K FGP iterations (Algorithm 2) on each of `batch` equally
+ * sized images followed by Eq. (18).
+ *   b           [batch][m][n] complex64 observation.
+ *   lambda_host [batch] host floats, lambda >= 0 per image. lambda = 0 or K = 0
+ *               gives x = P_C(b), the exact solution / Eq. (18) at q = 0.
+ *   support     [m][n] uint8 (0 = outside the support), shared by the batch; NULL = none.
+ *   x           [batch][m][n] complex64 output (may not alias b).
+ *   gap         [batch] doubles (device) receiving the duality gap
+ *               lambda * sum_groups(||(L x)_g|| - <q_g, (L x)_g>) >= 0 at the
+ *               returned x (derived from Appendix A); NULL = not computed.
+ *   state_in    dual state (layout above) to resume from after k0 iterations
+ *               already done; NULL = cold start q_0 = 0 (Algorithm 2, line 1), then k0 must be 0.
+ *   k0          iterations already performed (t_{k0} continues the t sequence).
+ *   state_out   dual state after k0 + K iterations, or NULL.
+ *   ckpt_every  0, or c > 0 to store the dual state at k = 0, c, 2c, ... < K in
+ *               `saved` (needed by ctv_denoise_backward); requires state_in == NULL.
+ *   saved       [ceil(K/c)][batch][2][m][n][4] floats, or NULL when ckpt_every = 0.
+ *   ws          workspace of at least ctv_workspace_size() bytes.
+ * Errors: CTV_ERR_INVALID_ARG (null/negative/out-of-range arguments, unknown
+ * kind/constraint, alpha outside [0,1], lambda < 0 or non-finite, m or n < 1,
+ * struct_size mismatch), CTV_ERR_WORKSPACE (ws_bytes too small),
+ * CTV_ERR_HIP (a launch failed). */
+ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n, const float* b,
+                       const float* lambda_host, const uint8_t* support, float* x, double* gap,
+                       const float* state_in, int32_t k0, float* state_out, int32_t ckpt_every,
+                       float* saved, void* ws, size_t ws_bytes, ctv_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched ragged denoising: many images of different sizes, each with its own
+ * lambda, TV kind, alpha and K, in one HIP-graph launch. Per image the result
+ * equals ctv_denoise on that image alone (bitwise, for the same fuse setting).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t offset;          /* first pixel of the image in the packed buffers (complex elements) */
+  int32_t m, n;            /* rows, columns (>= 1) */
+  float lambda;            /* >= 0 */
+  int32_t tv_kind;         /* CTV_TV_* */
+  float alpha;             /* [0, 1] */
+  int32_t iters;           /* K >= 0 */
+  int64_t support_offset;  /* byte offset of this image's m x n mask in the packed support buffer; -1 = none */
+} ctv_image_desc;
+
+typedef struct ctv_batched_plan ctv_batched_plan;
+
+/* Builds the tile work list, the momentum table and a HIP graph with one
+ * kernel node per fused step; allocates the plan's device tables. `common`
+ * supplies constraint and fuse (tv_kind/alpha/iters are taken per image).
+ * Images must not overlap in the packed buffers. */
+ctv_status ctv_batched_plan_create(const ctv_image_desc* descs_host, int32_t count,
+                                   const ctv_params* common, ctv_batched_plan** plan);
+ctv_status ctv_batched_workspace_size(const ctv_batched_plan* plan, size_t* ws_bytes);
+/* Runs the plan: b_packed and x_packed are complex64 buffers addressed by the
+ * descriptors' offsets; support_packed is a uint8 buffer (NULL if no image has
+ * a mask). One graph launch on `stream`; kernel arguments are refreshed when
+ * the pointers change between calls. */
+ctv_status ctv_denoise_batched(ctv_batched_plan* plan, const float* b_packed,
+                               const uint8_t* support_packed, float* x_packed, void* ws,
+                               size_t ws_bytes, ctv_stream_t stream);
+ctv_status ctv_batched_plan_destroy(ctv_batched_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * ctv_denoise_backward - exact reverse-mode derivative of the K-step map
+ * (b, lambda) -> x of ctv_denoise (chain rule through Algorithm 2 and Eq. 18).
+ * Requires the forward call's checkpoints (ckpt_every > 0, same b, lambda,
+ * support and params). Complex gradients use the real-pair convention of
+ * Section II: grad = dL/dRe + i dL/dIm (what PyTorch returns for a real loss).
+ * At the non-smooth points of the projections the Jacobian is the identity
+ * when the norm is <= the radius (zero for a zero radius).
+ *   grad_x       [batch][m][n] complex64 incoming gradient.
+ *   grad_b       [batch][m][n] complex64 output.
+ *   grad_lambda  [batch] floats (device) output; 0 where lambda = 0 or K = 0.
+ *   ws           at least ctv_backward_workspace_size() bytes.
+ * ------------------------------------------------------------------------- */
+ctv_status ctv_backward_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
+                                       int32_t ckpt_every, size_t* ws_bytes);
+ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
+                                const float* b, const float* lambda_host, const uint8_t* support,
+                                int32_t ckpt_every, const float* saved, const float* grad_x,
+                                float* grad_b, float* grad_lambda, void* ws, size_t ws_bytes,
+                                ctv_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Phase retrieval (Section V): FISTA (Algorithm 1) on
+ *   F(x) + tau ||x||_TV + I_C(x),  F(x) = sum_d 0.5 || |A_d x| - sqrt(y_d) ||^2 (Eq. 24),
+ * A_d = angular-spectrum propagation over distance d (Eq. 23), gradient Eq. (27),
+ * prox = ctv FGP with lambda = tau * gamma (Eq. 15), cold dual start per prox.
+ * m and n must be powers of two in [2, 4096].
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t struct_size;          /* sizeof(pr_params) */
+  int32_t num_meas;              /* D >= 1 */
+  const double* distances_host;  /* [D] propagation distances (m) */
+  double wavelength;             /* illumination wavelength (m), > 0 */
+  double pixel;                  /* sampling pitch (m), > 0 */
+  float tau;                     /* TV weight >= 0 */
+  float gamma;                   /* step size > 0 (0 = 1/D) */
+  int32_t outer_iters;           /* K_out >= 0 */
+  ctv_params inner;              /* prox: kind, alpha, constraint, iters = K_in, fuse */
+  int32_t init_backprop;         /* 1: x0 = (1/D) sum_d A_d^H sqrt(y_d); 0: x0 is read from x */
+  int32_t accelerate;            /* 1: FISTA (Algorithm 1); 0: plain proximal gradient (Eq. 14) */
+} pr_params;
+
+ctv_status pr_workspace_size(const pr_params* p, int32_t m, int32_t n, size_t* ws_bytes);
+/*   y           [D][m][n] float intensities (>= 0).
+ *   x           [m][n] complex64: input x0 when init_backprop = 0; output x_K.
+ *   loss_trace  [K_out] floats (device) receiving F(z_k) at each gradient point, or NULL. */
+ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y, float* x,
+                        float* loss_trace, void* ws, size_t ws_bytes, ctv_stream_t stream);
+
+/* Stage entry points of the phase-retrieval path (same conventions).
+ * ctv_fft2: in-place-safe 2-D DFT of a complex64 [batch][m][n] array,
+ *   out = sum x exp(-2 pi i (jk'/m + kk'/n)) (inverse: + sign and 1/(m n)).
+ * pr_forward: out[d] = A_d x for every distance (out is [D][m][n] complex64).
+ * pr_gradient: grad = sum_d A_d^H[(A_d x / |A_d x|)(|A_d x| - sqrt(y_d))] (Eq. 27),
+ *   and loss (device float, may be NULL) = F(x). */
+ctv_status ctv_fft2(int32_t batch, int32_t m, int32_t n, const float* in, float* out,
+                    int32_t inverse, ctv_stream_t stream);
+ctv_status pr_forward(const pr_params* p, int32_t m, int32_t n, const float* x, float* out,
+                      void* ws, size_t ws_bytes, ctv_stream_t stream);
+ctv_status pr_gradient(const pr_params* p, int32_t m, int32_t n, const float* y, const float* x,
+                       float* grad, float* loss, void* ws, size_t ws_bytes, ctv_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTV_H */

@@ -1,0 +1,281 @@
+"""Python API over the C ABI. Argument marshalling only: tensors must already be
+on the GPU; every step of the solver runs in the HIP library."""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import call, make_params
+
+
+def _stream(dev):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_cuda(t, name, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _lams(lam, batch):
+    if isinstance(lam, torch.Tensor):
+        lam = lam.detach().cpu().reshape(-1).tolist()
+    elif isinstance(lam, (int, float)):
+        lam = [float(lam)] * batch
+    lam = [float(v) for v in lam]
+    if len(lam) == 1 and batch > 1:
+        lam = lam * batch
+    if len(lam) != batch:
+        raise ValueError("lambda must be a scalar or have one value per image")
+    return (ctypes.c_float * batch)(*lam)
+
+
+def workspace_size(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0,
+                   ckpt_every=0):
+    """(workspace bytes, checkpoint bytes) for ``denoise``."""
+    p = make_params(kind, alpha, constraint, iters, fuse)
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    call("ctv_workspace_size", ctypes.byref(p), batch, m, n, ckpt_every, ctypes.byref(ws), ctypes.byref(sv))
+    return ws.value, sv.value
+
+
+def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, iters=100, fuse=0,
+            gap=False, state=None, k0=0, return_state=False, ckpt_every=0, saved=None, out=None,
+            workspace=None):
+    """K FGP iterations (Algorithm 2) + Eq. (18) on the GPU.
+
+    b: complex64 CUDA tensor [m, n] or [B, m, n]. lam: float or B floats.
+    support: uint8 [m, n] or None. Returns x (and the duality gap as a float64
+    tensor [B] when gap=True, and the dual state when return_state=True).
+    """
+    _require_cuda(b, "b", torch.complex64)
+    squeeze = b.dim() == 2
+    bb = b.unsqueeze(0) if squeeze else b
+    B, m, n = bb.shape
+    dev = bb.device
+    p = make_params(kind, alpha, constraint, iters, fuse)
+    if support is not None:
+        _require_cuda(support, "support", torch.uint8)
+        if tuple(support.shape) != (m, n):
+            raise ValueError("support must be [m, n]")
+    x = out if out is not None else torch.empty_like(bb)
+    _require_cuda(x, "out", torch.complex64)
+    ws_bytes, sv_bytes = workspace_size(m, n, B, kind, alpha, constraint, iters, fuse, ckpt_every)
+    ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    g = torch.empty(B, dtype=torch.float64, device=dev) if gap else None
+    st_out = torch.empty((B, 2, m, n, 4), dtype=torch.float32, device=dev) if return_state else None
+    if state is not None:
+        _require_cuda(state, "state", torch.float32)
+    if ckpt_every and saved is None and sv_bytes:
+        saved = torch.empty(sv_bytes // 4, dtype=torch.float32, device=dev)
+    call("ctv_denoise", ctypes.byref(p), B, m, n, _ptr(bb), _lams(lam, B), _ptr(support), _ptr(x),
+         _ptr(g), _ptr(state), int(k0), _ptr(st_out), int(ckpt_every), _ptr(saved), _ptr(ws),
+         ws.numel(), _stream(dev))
+    x = x[0] if squeeze else x
+    res = [x]
+    if gap:
+        res.append(g)
+    if return_state:
+        res.append(st_out)
+    if ckpt_every:
+        res.append(saved)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def denoise_backward(b, lam, grad_x, saved, kind="1i", alpha=0.5, constraint="modulus", support=None,
+                     iters=100, fuse=0, ckpt_every=10):
+    """Reverse pass of the K-step map; returns (grad_b, grad_lambda[B])."""
+    _require_cuda(b, "b", torch.complex64)
+    _require_cuda(grad_x, "grad_x", torch.complex64)
+    squeeze = b.dim() == 2
+    bb = b.unsqueeze(0) if squeeze else b
+    gx = grad_x.unsqueeze(0) if squeeze else grad_x
+    B, m, n = bb.shape
+    dev = bb.device
+    p = make_params(kind, alpha, constraint, iters, fuse)
+    ws_bytes = ctypes.c_size_t()
+    call("ctv_backward_workspace_size", ctypes.byref(p), B, m, n, ckpt_every, ctypes.byref(ws_bytes))
+    ws = torch.empty(ws_bytes.value, dtype=torch.uint8, device=dev)
+    gb = torch.empty_like(bb)
+    gl = torch.empty(B, dtype=torch.float32, device=dev)
+    call("ctv_denoise_backward", ctypes.byref(p), B, m, n, _ptr(bb), _lams(lam, B), _ptr(support),
+         int(ckpt_every), _ptr(saved), _ptr(gx.contiguous()), _ptr(gb), _ptr(gl), _ptr(ws), ws.numel(),
+         _stream(dev))
+    return (gb[0] if squeeze else gb), gl
+
+
+class CTVDenoise(torch.autograd.Function):
+    """x = FGP_K(b, lambda) with gradients for b (complex64) and lambda.
+
+    apply(b, lam, kind, alpha, constraint, support, iters, ckpt_every, fuse).
+    lam may be a Python float (no gradient) or a float32 tensor of shape [] or
+    [B]; a scalar tensor receives the sum of the per-image gradients.
+    """
+
+    @staticmethod
+    def forward(ctx, b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, iters=50,
+                ckpt_every=10, fuse=0):
+        lam_vals = lam.detach() if isinstance(lam, torch.Tensor) else lam
+        x, saved = denoise(b, lam_vals, kind, alpha, constraint, support, iters, fuse,
+                           ckpt_every=ckpt_every)
+        ctx.save_for_backward(b, saved)
+        ctx.lam = lam_vals.cpu().reshape(-1).tolist() if isinstance(lam_vals, torch.Tensor) else lam_vals
+        ctx.lam_shape = lam.shape if isinstance(lam, torch.Tensor) else None
+        ctx.cfg = (kind, alpha, constraint, support, iters, fuse, ckpt_every)
+        return x
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        b, saved = ctx.saved_tensors
+        kind, alpha, constraint, support, iters, fuse, ckpt_every = ctx.cfg
+        gb, gl = denoise_backward(b, ctx.lam, grad_x.contiguous(), saved, kind, alpha, constraint, support,
+                                  iters, fuse, ckpt_every)
+        glam = None
+        if ctx.lam_shape is not None:
+            glam = gl.sum().reshape(ctx.lam_shape) if len(ctx.lam_shape) == 0 or ctx.lam_shape.numel() == 1 \
+                else gl.reshape(ctx.lam_shape)
+        return gb, glam, None, None, None, None, None, None, None
+
+
+class BatchedPlan:
+    """Ragged batch of images denoised in one HIP-graph launch.
+
+    images: list of dicts with keys m, n, lam, kind ('1i'..'2a'), alpha,
+    iters and optionally has_support. Images are packed back to back in the
+    order given; ``offsets`` gives each image's first pixel.
+    """
+
+    def __init__(self, images, constraint="modulus", fuse=0):
+        descs = (_lib.ImageDesc * len(images))()
+        off = 0
+        soff = 0
+        self.offsets, self.support_offsets, self.shapes = [], [], []
+        for d, im in zip(descs, images):
+            m, n = int(im["m"]), int(im["n"])
+            d.offset = off
+            d.m, d.n = m, n
+            d.lam = float(im["lam"])
+            d.tv_kind = _lib.KINDS[im.get("kind", "1i")]
+            d.alpha = float(im.get("alpha", 0.5))
+            d.iters = int(im.get("iters", 100))
+            if im.get("has_support"):
+                d.support_offset = soff
+                self.support_offsets.append(soff)
+                soff += m * n
+            else:
+                d.support_offset = -1
+                self.support_offsets.append(-1)
+            self.offsets.append(off)
+            self.shapes.append((m, n))
+            off += m * n
+        self.total_pixels = off
+        self.support_bytes = soff
+        common = make_params("1i", 0.5, constraint, 0, fuse)
+        h = ctypes.c_void_p()
+        call("ctv_batched_plan_create", descs, len(images), ctypes.byref(common), ctypes.byref(h))
+        self._h = h
+        ws = ctypes.c_size_t()
+        call("ctv_batched_workspace_size", self._h, ctypes.byref(ws))
+        self.ws_bytes = ws.value
+        self._ws = None
+
+    def pack(self, imgs, device="cuda"):
+        flat = torch.empty(self.total_pixels, dtype=torch.complex64, device=device)
+        for o, (m, n), im in zip(self.offsets, self.shapes, imgs):
+            flat[o:o + m * n] = torch.as_tensor(im).reshape(-1).to(device=device, dtype=torch.complex64)
+        return flat
+
+    def unpack(self, flat):
+        return [flat[o:o + m * n].reshape(m, n) for o, (m, n) in zip(self.offsets, self.shapes)]
+
+    def run(self, b_packed, support_packed=None, out=None):
+        _require_cuda(b_packed, "b_packed", torch.complex64)
+        dev = b_packed.device
+        x = out if out is not None else torch.empty_like(b_packed)
+        if self._ws is None or self._ws.device != dev:
+            self._ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        call("ctv_denoise_batched", self._h, _ptr(b_packed), _ptr(support_packed), _ptr(x), _ptr(self._ws),
+             self._ws.numel(), _stream(dev))
+        return x
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            call("ctv_batched_plan_destroy", self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _pr_params(distances, wavelength, pixel, tau, gamma, outer, inner_iters, kind, alpha, constraint,
+               init_backprop, accelerate, fuse):
+    dist = (ctypes.c_double * len(distances))(*[float(d) for d in distances])
+    p = _lib.PrParams(ctypes.sizeof(_lib.PrParams), len(distances), dist, float(wavelength), float(pixel),
+                      float(tau), float(gamma), int(outer), make_params(kind, alpha, constraint, inner_iters, fuse),
+                      int(init_backprop), int(accelerate))
+    return p, dist
+
+
+def _pr_ws(p, m, n, dev):
+    ws = ctypes.c_size_t()
+    call("pr_workspace_size", ctypes.byref(p), m, n, ctypes.byref(ws))
+    return torch.empty(max(ws.value, 1), dtype=torch.uint8, device=dev)
+
+
+def phase_retrieval(y, distances, wavelength, pixel, tau=0.01, gamma=0.0, outer=100, inner=20, kind="1i",
+                    alpha=0.5, constraint="modulus", x0=None, accelerate=True, fuse=0, loss=False):
+    """Algorithm 1 with the FGP prox; y: float32 CUDA [D, m, n] intensities."""
+    _require_cuda(y, "y", torch.float32)
+    D, m, n = y.shape
+    dev = y.device
+    p, _keep = _pr_params(distances, wavelength, pixel, tau, gamma, outer, inner, kind, alpha, constraint,
+                          x0 is None, accelerate, fuse)
+    x = torch.empty((m, n), dtype=torch.complex64, device=dev) if x0 is None else x0.clone()
+    lt = torch.empty(max(outer, 1), dtype=torch.float32, device=dev) if loss else None
+    ws = _pr_ws(p, m, n, dev)
+    call("pr_prox_grad", ctypes.byref(p), m, n, _ptr(y), _ptr(x), _ptr(lt), _ptr(ws), ws.numel(), _stream(dev))
+    return (x, lt[:outer]) if loss else x
+
+
+def pr_forward(x, distances, wavelength, pixel):
+    _require_cuda(x, "x", torch.complex64)
+    m, n = x.shape
+    p, _keep = _pr_params(distances, wavelength, pixel, 0, 1, 0, 0, "1i", 0.5, "modulus", 0, 1, 0)
+    out = torch.empty((len(distances), m, n), dtype=torch.complex64, device=x.device)
+    ws = _pr_ws(p, m, n, x.device)
+    call("pr_forward", ctypes.byref(p), m, n, _ptr(x), _ptr(out), _ptr(ws), ws.numel(), _stream(x.device))
+    return out
+
+
+def pr_gradient(x, y, distances, wavelength, pixel):
+    _require_cuda(x, "x", torch.complex64)
+    _require_cuda(y, "y", torch.float32)
+    m, n = x.shape
+    p, _keep = _pr_params(distances, wavelength, pixel, 0, 1, 0, 0, "1i", 0.5, "modulus", 0, 1, 0)
+    g = torch.empty_like(x)
+    lv = torch.empty(1, dtype=torch.float32, device=x.device)
+    ws = _pr_ws(p, m, n, x.device)
+    call("pr_gradient", ctypes.byref(p), m, n, _ptr(y), _ptr(x), _ptr(g), _ptr(lv), _ptr(ws), ws.numel(),
+         _stream(x.device))
+    return g, lv
+
+
+def fft2(x, inverse=False):
+    _require_cuda(x, "x", torch.complex64)
+    squeeze = x.dim() == 2
+    xx = x.unsqueeze(0) if squeeze else x
+    B, m, n = xx.shape
+    out = torch.empty_like(xx)
+    call("ctv_fft2", B, m, n, _ptr(xx), _ptr(out), int(bool(inverse)), _stream(x.device))
+    return out[0] if squeeze else out

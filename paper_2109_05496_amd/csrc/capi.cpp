@@ -1,0 +1,227 @@
+// Host side of the C ABI: argument validation, workspace layout, the FP64
+// momentum schedule of Algorithm 2, and the launch schedule of the fused
+// forward kernel (plain batches). Batched plans, the adjoint and the
+// phase-retrieval driver live in their own translation units.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctv.h"
+#include "ctv_host.hpp"
+#include "ctv_kernels.hpp"
+
+namespace ctv {
+
+thread_local std::string g_last_error;
+
+ctv_status fail(ctv_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+ctv_status hip_fail(hipError_t e, const char* where) {
+  return fail(CTV_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+ctv_status validate_params(const ctv_params* p) {
+  if (!p) return fail(CTV_ERR_INVALID_ARG, "params is NULL");
+  if (p->struct_size != sizeof(ctv_params)) return fail(CTV_ERR_INVALID_ARG, "ctv_params.struct_size mismatch");
+  if (p->tv_kind < CTV_TV_1I || p->tv_kind > CTV_TV_2A) return fail(CTV_ERR_INVALID_ARG, "unknown tv_kind");
+  if (p->constraint != CTV_C_NONE && p->constraint != CTV_C_MODULUS)
+    return fail(CTV_ERR_INVALID_ARG, "unknown constraint");
+  if (!(p->alpha >= 0.0f && p->alpha <= 1.0f)) return fail(CTV_ERR_INVALID_ARG, "alpha must lie in [0, 1]");
+  if (p->iters < 0) return fail(CTV_ERR_INVALID_ARG, "iters must be >= 0");
+  if (p->fuse < 0 || p->fuse > kMaxFuse) return fail(CTV_ERR_INVALID_ARG, "fuse must lie in [0, 16]");
+  return CTV_OK;
+}
+
+ctv_status validate_lambda(float lam) {
+  if (!(lam >= 0.0f) || !std::isfinite(lam)) return fail(CTV_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  return CTV_OK;
+}
+
+Radii make_radii(int kind, float alpha) {
+  Radii R;
+  if (kind == CTV_TV_2I || kind == CTV_TV_2A) {
+    const double a = alpha, s = 1.0 - (double)alpha;
+    R.ra = (float)a;
+    R.ra2 = (float)(a * a);
+    R.sa = (float)s;
+    R.sa2 = (float)(s * s);
+  } else {
+    R.ra = R.ra2 = R.sa = R.sa2 = 1.0f;
+  }
+  return R;
+}
+
+void momentum_table(int kmax, std::vector<float>& beta) {
+  // beta[k] = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+  // (Algorithm 2, lines 4-5), evaluated in float64 and rounded once.
+  beta.assign((size_t)kmax + 2, 0.0f);
+  double t = 1.0;
+  for (int k = 1; k <= kmax + 1; ++k) {
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    beta[(size_t)k] = (float)((t - 1.0) / tn);
+    t = tn;
+  }
+}
+
+float step_of(float lam) {
+  // 1/(16 lambda^2) times the 2 lambda of Eq. (19); lambda = 0 gives a zero
+  // step, which keeps q = 0 and returns x = P_C(b) exactly.
+  return lam > 0.0f ? (float)(1.0 / (8.0 * (double)lam)) : 0.0f;
+}
+
+Tiling choose_tiling(int fuse, int iters, int m, int n, int batch) {
+  (void)m;
+  (void)n;
+  (void)batch;
+  Tiling t;
+  t.T = fuse > 0 ? fuse : 4;
+  if (iters > 0) t.T = std::min(t.T, iters);
+  t.T = std::max(t.T, 1);
+  // the epilogue launch needs a halo of T + 1 and at least one output row
+  t.rh = (2 * (t.T + 1) + 8 <= 32) ? 32 : 64;
+  if (fuse == 0) t.rh = 64;
+  return t;
+}
+
+size_t state_bytes(long long batch, long long m, long long n) { return (size_t)(batch * 2 * m * n * 16); }
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int gap_blocks_per_image(long long px) {
+  long long b = (px + 1023) / 1024;
+  return (int)std::max(1LL, std::min(256LL, b));
+}
+
+size_t denoise_ws_bytes(int batch, int m, int n) {
+  const size_t st = align_up(state_bytes(batch, m, n));
+  const size_t gap = align_up((size_t)batch * gap_blocks_per_image((long long)m * n) * sizeof(double));
+  return 2 * st + gap;
+}
+
+}  // namespace ctv
+
+using namespace ctv;
+
+extern "C" {
+
+int32_t ctv_version(void) { return 100; }
+
+const char* ctv_last_error(void) { return g_last_error.c_str(); }
+
+ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
+                              int32_t ckpt_every, size_t* ws_bytes, size_t* saved_bytes) {
+  ctv_status st = validate_params(p);
+  if (st) return st;
+  if (batch < 1 || m < 1 || n < 1) return fail(CTV_ERR_INVALID_ARG, "batch, m and n must be >= 1");
+  if (ckpt_every < 0) return fail(CTV_ERR_INVALID_ARG, "ckpt_every must be >= 0");
+  if (ws_bytes) *ws_bytes = denoise_ws_bytes(batch, m, n);
+  if (saved_bytes) {
+    long long slots = 0;
+    if (ckpt_every > 0 && p->iters > 0) slots = (p->iters + ckpt_every - 1) / ckpt_every - 1;
+    *saved_bytes = (size_t)slots * state_bytes(batch, m, n);
+  }
+  return CTV_OK;
+}
+
+ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n, const float* b,
+                       const float* lambda_host, const uint8_t* support, float* x, double* gap,
+                       const float* state_in, int32_t k0, float* state_out, int32_t ckpt_every,
+                       float* saved, void* ws, size_t ws_bytes, ctv_stream_t stream) {
+  ctv_status st = validate_params(p);
+  if (st) return st;
+  if (batch < 1 || m < 1 || n < 1) return fail(CTV_ERR_INVALID_ARG, "batch, m and n must be >= 1");
+  if (!b || !x || !lambda_host) return fail(CTV_ERR_INVALID_ARG, "b, x and lambda_host must be non-NULL");
+  if (b == x) return fail(CTV_ERR_INVALID_ARG, "x must not alias b");
+  if (state_out && state_out == state_in) return fail(CTV_ERR_INVALID_ARG, "state_out must not alias state_in");
+  for (int i = 0; i < batch; ++i) {
+    st = validate_lambda(lambda_host[i]);
+    if (st) return st;
+  }
+  if (k0 < 0) return fail(CTV_ERR_INVALID_ARG, "k0 must be >= 0");
+  if (!state_in && k0 != 0) return fail(CTV_ERR_INVALID_ARG, "k0 > 0 requires state_in");
+  if (ckpt_every < 0) return fail(CTV_ERR_INVALID_ARG, "ckpt_every must be >= 0");
+  if (ckpt_every > 0 && state_in) return fail(CTV_ERR_INVALID_ARG, "checkpoints require a cold start");
+  const long long slots = (ckpt_every > 0 && p->iters > 0) ? (p->iters + ckpt_every - 1) / ckpt_every - 1 : 0;
+  if (slots > 0 && !saved) return fail(CTV_ERR_INVALID_ARG, "saved is NULL but checkpoints are requested");
+  if ((long long)k0 + p->iters > (1LL << 30)) return fail(CTV_ERR_INVALID_ARG, "k0 + iters too large");
+  if (!ws) return fail(CTV_ERR_INVALID_ARG, "ws is NULL");
+  const size_t need = denoise_ws_bytes(batch, m, n);
+  if (ws_bytes < need) return fail(CTV_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long px = (long long)m * n;
+  const size_t st_full = state_bytes(batch, m, n);
+  char* wsb = static_cast<char*>(ws);
+  float* bufA = reinterpret_cast<float*>(wsb);
+  float* bufB = reinterpret_cast<float*>(wsb + align_up(st_full));
+  double* partial = reinterpret_cast<double*>(wsb + 2 * align_up(st_full));
+  const Tiling tl = choose_tiling(p->fuse, p->iters, m, n, batch);
+  std::vector<float> beta;
+  momentum_table(k0 + p->iters + 1, beta);
+  const Radii R = make_radii(p->tv_kind, p->alpha);
+
+  for (int c0 = 0; c0 < batch; c0 += kPlainChunk) {
+    const int cb = std::min(kPlainChunk, batch - c0);
+    const long long img_px = px * c0;            // pixel offset of the chunk
+    const long long st_off = 2 * px * c0 * 4;    // float offset of the chunk in a state buffer
+    FgpPlainArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.b = b + 2 * img_px;
+    a.mask = support;
+    a.m = m;
+    a.n = n;
+    a.R = R;
+    for (int i = 0; i < cb; ++i) {
+      a.lam[i] = lambda_host[c0 + i];
+      a.c[i] = step_of(lambda_host[c0 + i]);
+    }
+    const float* src = state_in ? state_in + st_off : nullptr;
+    int k = k0;
+    const int kend = k0 + p->iters;
+    do {
+      int Tl = std::min(tl.T, kend - k);
+      if (ckpt_every > 0) Tl = std::min(Tl, (k / ckpt_every + 1) * ckpt_every - k);
+      const bool last = (k + Tl == kend);
+      float* dst;
+      float* other = (src == bufA + st_off) ? bufB + st_off : bufA + st_off;
+      if (last)
+        dst = state_out ? state_out + st_off : (gap ? other : nullptr);
+      else if (ckpt_every > 0 && (k + Tl) % ckpt_every == 0)
+        dst = saved + (size_t)((k + Tl) / ckpt_every - 1) * (st_full / 4) + st_off;
+      else
+        dst = other;
+      a.st_in = src;
+      a.st_out = dst;
+      a.x = last ? x + 2 * img_px : nullptr;
+      a.T = Tl;
+      a.halo = Tl + (last ? 1 : 0);
+      a.halo = std::max(a.halo, 1);
+      for (int i = 0; i < kMaxFuse; ++i) a.beta[i] = (i < Tl) ? beta[(size_t)(k + 1 + i)] : 0.0f;
+      a.tiles_x = (int)((n + (64 - 2 * a.halo) - 1) / (64 - 2 * a.halo));
+      a.tiles_y = (int)((m + (tl.rh - 2 * a.halo) - 1) / (tl.rh - 2 * a.halo));
+      hipError_t e = launch_fgp_plain(a, p->tv_kind, p->constraint, tl.rh, cb, s);
+      if (e != hipSuccess) return hip_fail(e, "fgp launch");
+      src = dst;
+      k += Tl;
+    } while (k < kend);
+    if (gap) {
+      GapArgs ga;
+      for (int i = 0; i < cb; ++i) ga.lam[i] = lambda_host[c0 + i];
+      const float* qstate = src;
+      if (!qstate) return fail(CTV_ERR_HIP, "internal: no final state for the gap");
+      hipError_t e = launch_gap(x + 2 * img_px, qstate, m, n, cb, p->tv_kind, R, ga, partial,
+                                gap_blocks_per_image(px), gap + c0, s);
+      if (e != hipSuccess) return hip_fail(e, "gap launch");
+    }
+  }
+  return CTV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Per-pixel operators of the complex constrained TV solver, shared by every
+// kernel of the HIP path (plain, batched, adjoint) so that they all perform the
+// same float32 operations in the same order and agree bit for bit.
+//
+// Data layout (padded): the dual variable of a pixel is one float4
+// (r1, s1, r2, s2): the vertical difference pair Q1 = r1 + i s1 and the
+// horizontal pair Q2 = r2 + i s2 (Proposition 1's q = (r1, r2, s1, s2)).
+// Q1 on the last row and Q2 on the last column do not exist in the paper; they
+// are held at exactly 0, which makes the paper's separate boundary formulas
+// (Eqs. 17, 20, 34, 35) coincide with the interior ones.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ctv_types.hpp"
+
+namespace ctv {
+
+// P_C of one pixel: x / max{1, |x|} (Eq. 26) when the modulus constraint is
+// on, then forced to 0 outside the support.
+template <int CONSTR>
+__device__ __forceinline__ float2 proj_c(float2 w, bool inside) {
+  float2 y = w;
+  if (CONSTR == C_MOD) {
+    const float n2 = fmaf(w.x, w.x, w.y * w.y);
+    const float s = (n2 > 1.0f) ? rsqrtf(n2) : 1.0f;
+    y.x = w.x * s;
+    y.y = w.y * s;
+  }
+  if (!inside) {
+    y.x = 0.0f;
+    y.y = 0.0f;
+  }
+  return y;
+}
+
+// P_S of one pixel's dual group(s).
+//   1i: the 4-vector onto the unit ball (Eq. 20)
+//   1a: each complex direction pair onto the unit disc (Eq. 33)
+//   2i: (r1, r2) onto the alpha-disc, (s1, s2) onto the (1-alpha)-disc (Eq. 35)
+//   2a: each real entry clipped to [-alpha, alpha] or [-(1-alpha), 1-alpha] (Eq. 37)
+// A vector is scaled only when its squared norm exceeds the squared radius;
+// ties return the input, which equals the scaled value.
+template <int KIND>
+__device__ __forceinline__ float4 proj_s(float4 g, const Radii& R) {
+  if (KIND == K1I) {
+    const float n2 = fmaf(g.x, g.x, fmaf(g.y, g.y, fmaf(g.z, g.z, g.w * g.w)));
+    const float s = (n2 > 1.0f) ? rsqrtf(n2) : 1.0f;
+    return make_float4(g.x * s, g.y * s, g.z * s, g.w * s);
+  } else if (KIND == K1A) {
+    const float n1 = fmaf(g.x, g.x, g.y * g.y);
+    const float n2 = fmaf(g.z, g.z, g.w * g.w);
+    const float s1 = (n1 > 1.0f) ? rsqrtf(n1) : 1.0f;
+    const float s2 = (n2 > 1.0f) ? rsqrtf(n2) : 1.0f;
+    return make_float4(g.x * s1, g.y * s1, g.z * s2, g.w * s2);
+  } else if (KIND == K2I) {
+    const float nr = fmaf(g.x, g.x, g.z * g.z);
+    const float ns = fmaf(g.y, g.y, g.w * g.w);
+    const float fr = (nr > R.ra2) ? R.ra * rsqrtf(nr) : 1.0f;
+    const float fs = (ns > R.sa2) ? R.sa * rsqrtf(ns) : 1.0f;
+    return make_float4(g.x * fr, g.y * fs, g.z * fr, g.w * fs);
+  } else {
+    return make_float4(fminf(fmaxf(g.x, -R.ra), R.ra), fminf(fmaxf(g.y, -R.sa), R.sa),
+                       fminf(fmaxf(g.z, -R.ra), R.ra), fminf(fmaxf(g.w, -R.sa), R.sa));
+  }
+}
+
+// w = b - lambda * L^T(r) at one pixel, per channel
+//   (L^T a)_{j,k} = a1_{j,k} - a1_{j-1,k} + a2_{j,k} - a2_{j,k-1},
+// the adjoint of the forward differences of Eqs. (5)-(6); `up` is the (r1, s1)
+// pair of pixel (j-1, k) and `left` the (r2, s2) pair of (j, k-1), both zero
+// outside the image.
+__device__ __forceinline__ float2 dual_to_primal(float2 b, float4 r, float2 up, float2 left,
+                                                 float lam) {
+  const float du = (r.x - up.x) + (r.z - left.x);
+  const float dv = (r.y - up.y) + (r.w - left.y);
+  return make_float2(fmaf(-lam, du, b.x), fmaf(-lam, dv, b.y));
+}
+
+// g = r + L(y) / (8 lambda): the dual gradient step of Algorithm 2, line 3,
+// with grad h from Eq. (19) and step 1/(16 lambda^2). `down` is y at (j+1, k),
+// `right` y at (j, k+1); the differences that do not exist (last row /
+// last column) are kept at zero.
+__device__ __forceinline__ float4 dual_step(float4 r, float2 y, float2 down, float2 right,
+                                            float c, bool has_down, bool has_right) {
+  float4 g;
+  g.x = has_down ? fmaf(c, y.x - down.x, r.x) : 0.0f;
+  g.y = has_down ? fmaf(c, y.y - down.y, r.y) : 0.0f;
+  g.z = has_right ? fmaf(c, y.x - right.x, r.z) : 0.0f;
+  g.w = has_right ? fmaf(c, y.y - right.y, r.w) : 0.0f;
+  return g;
+}
+
+// r_{k+1} = q_k + beta_k (q_k - q_{k-1})  (Algorithm 2, line 5).
+__device__ __forceinline__ float4 extrapolate(float4 qn, float4 qo, float beta) {
+  return make_float4(fmaf(beta, qn.x - qo.x, qn.x), fmaf(beta, qn.y - qo.y, qn.y),
+                     fmaf(beta, qn.z - qo.z, qn.z), fmaf(beta, qn.w - qo.w, qn.w));
+}
+
+// Consecutive workgroup ids are spread round-robin over the 8 XCDs of an
+// MI355X; give each XCD one contiguous range of tiles so neighbouring tiles
+// (which re-read each other's halos) share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int q = nblocks / kXcd, rem = nblocks % kXcd;
+  const int x = bid % kXcd, i = bid / kXcd;
+  return x * q + (x < rem ? x : rem) + i;
+}
+
+}  // namespace ctv

@@ -1,0 +1,74 @@
+// Kernel argument blocks and host launchers of the HIP path (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ctv_types.hpp"
+
+namespace ctv {
+
+constexpr int kPlainChunk = 32;  // images per plain launch (per-image lambda lives in kernargs)
+
+struct FgpPlainArgs {
+  const float* b;        // chunk base, [chunk][m][n] complex64
+  const uint8_t* mask;   // [m][n] or nullptr
+  const float* st_in;    // [chunk][2][m][n][4] or nullptr (cold start)
+  float* st_out;         // same layout or nullptr
+  float* x;              // [chunk][m][n] complex64 or nullptr
+  int m, n;
+  int tiles_x, tiles_y;
+  int halo;
+  int T;
+  Radii R;
+  float beta[kMaxFuse];  // beta[i] = (t_k - 1)/t_{k+1} for the i-th fused iteration k
+  float lam[kPlainChunk];
+  float c[kPlainChunk];  // 1 / (8 lambda)
+};
+
+struct BatchImage {
+  long long offset;          // first pixel in the packed image buffers
+  long long support_offset;  // byte offset of the mask, -1 = none
+  int m, n;
+  int kind;
+  int iters;                 // 0 for lambda = 0 (x = P_C(b))
+  float lam, c;
+  Radii R;
+};
+
+struct BatchTile {
+  int image, tx, ty, pad;
+};
+
+struct FgpBatchedArgs {
+  const BatchTile* tiles;
+  const BatchImage* images;
+  const float* beta_table;  // beta_table[k] = (t_k - 1)/t_{k+1}, k >= 1
+  const float* b;
+  const uint8_t* support;
+  const float* st_in;       // packed [2 * pixels][4] per image at 2 * offset
+  float* st_out;
+  float* x;
+  int k0;                   // iterations completed before this launch
+  int T;                    // iterations fused in this launch
+  int halo;
+};
+
+// Region rows supported by the tile kernels (64 columns each).
+inline bool valid_region_rows(int rh) { return rh == 16 || rh == 32 || rh == 64; }
+
+hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, int rh, int batch,
+                            hipStream_t s);
+const void* fgp_batched_kernel_ptr(int constr, int rh);
+hipError_t launch_fgp_batched(const FgpBatchedArgs& a, int constr, int rh, int nblocks,
+                              hipStream_t s);
+hipError_t launch_zero_f4(float* p, long long count_f4, hipStream_t s);
+hipError_t launch_project_c(const float* b, const uint8_t* mask, float* x, long long px, int batch,
+                            int constr, hipStream_t s);
+struct GapArgs {
+  float lam[kPlainChunk];
+};
+hipError_t launch_gap(const float* x, const float* state, int m, int n, int batch, int kind,
+                      Radii R, const GapArgs& lam, double* partial, int blocks_per_img,
+                      double* gap, hipStream_t s);
+
+}  // namespace ctv

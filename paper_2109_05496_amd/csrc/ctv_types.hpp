@@ -1,0 +1,17 @@
+// Types shared by host and device code of the HIP path (internal).
+#pragma once
+
+namespace ctv {
+
+enum Kind { K1I = 0, K1A = 1, K2I = 2, K2A = 3 };
+enum Constr { C_NONE = 0, C_MOD = 1 };
+
+constexpr int kMaxFuse = 16;
+
+// Radii of the dual balls: type-I uses 1; type-II uses alpha for the real
+// plane's dual (r) and 1 - alpha for the imaginary plane's dual (s).
+struct Radii {
+  float ra, ra2, sa, sa2;
+};
+
+}  // namespace ctv

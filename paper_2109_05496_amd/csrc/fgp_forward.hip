@@ -1,0 +1,415 @@
+// Forward FGP kernels for gfx950: several iterations of Algorithm 2 fused per
+// launch on LDS-staged tiles with a halo, the output step of Eq. (18), the
+// projection-only path, and the duality-gap reduction.
+//
+// Tile scheme: a workgroup of 256 threads (4 wave64s) owns a region of 64
+// columns x RH rows. Lane l holds column l; wave w holds rows w, w+4, w+8, ...
+// Each thread keeps its pixels' b, q_k and r_{k+1} in registers. One iteration:
+//   1. publish r (as the (r1,s1) and (r2,s2) pairs) to LDS;           barrier
+//   2. y = P_C(b - lambda L^T r) using the up / left neighbours; y -> LDS; barrier
+//   3. g = r + L(y)/(8 lambda) using the down / right neighbours,
+//      q' = P_S(g), r' = q' + beta (q' - q).
+// Values near the region edge go stale by one pixel per iteration, so after T
+// fused iterations the central (64 - 2H) x (RH - 2H) pixels are exact when the
+// halo H >= T (H >= T + 1 when the Eq. (18) epilogue runs in the same launch,
+// since x reads q one pixel up and left). Image borders are exact at any
+// distance: the differences that leave the image are zero by construction.
+#include <hip/hip_runtime.h>
+
+#include "ctv_device.hpp"
+#include "ctv_kernels.hpp"
+
+namespace ctv {
+
+constexpr int kRW = 64;
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+struct TileJob {
+  const float2* b;       // image (m x n)
+  const uint8_t* mask;   // image support or nullptr
+  const float4* st_in;   // [2][m][n] (q plane, r plane) or nullptr = cold start
+  float4* st_out;        // [2][m][n] or nullptr
+  float2* x;             // Eq. (18) output or nullptr
+  int m, n;
+  int tx, ty;
+  float lam, c;
+  Radii R;
+  int T;
+};
+
+template <int KIND, int CONSTR, bool MASK, int RH>
+__device__ __forceinline__ void fgp_tile(const TileJob& J, const int H, const float* sBeta,
+                                         float2* __restrict__ sA1, float2* __restrict__ sA2,
+                                         float2* __restrict__ sY) {
+  constexpr int PPT = RH / kWaves;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int OW = kRW - 2 * H, OH = RH - 2 * H;
+  const int c0 = J.tx * OW - H, r0 = J.ty * OH - H;
+  const int k = c0 + lane;
+  const bool kin = (k >= 0) && (k < J.n);
+  const bool has_left = k > 0;
+  const bool has_right = k < J.n - 1;
+  const long long plane = (long long)J.m * J.n;
+  const float2 zero2 = make_float2(0.0f, 0.0f);
+
+  float4 q[PPT], r[PPT];
+  float2 b[PPT];
+  bool inside[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int j = r0 + wave + kWaves * i;
+    const bool in = kin && j >= 0 && j < J.m;
+    q[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    r[i] = q[i];
+    b[i] = zero2;
+    inside[i] = false;
+    if (in) {
+      const long long p = (long long)j * J.n + k;
+      b[i] = J.b[p];
+      if (J.st_in) {
+        q[i] = J.st_in[p];
+        r[i] = J.st_in[plane + p];
+      }
+      inside[i] = MASK ? (J.mask[p] != 0) : true;
+    }
+  }
+
+  for (int it = 0; it < J.T; ++it) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int ry = wave + kWaves * i;
+      sA1[ry * kRW + lane] = make_float2(r[i].x, r[i].y);
+      sA2[ry * kRW + lane] = make_float2(r[i].z, r[i].w);
+    }
+    __syncthreads();
+    float2 y[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int ry = wave + kWaves * i;
+      const int j = r0 + ry;
+      const float2 up = (j > 0) ? sA1[(ry > 0 ? ry - 1 : 0) * kRW + lane] : zero2;
+      const float2 left = has_left ? sA2[ry * kRW + (lane > 0 ? lane - 1 : 0)] : zero2;
+      y[i] = proj_c<CONSTR>(dual_to_primal(b[i], r[i], up, left, J.lam), inside[i]);
+      sY[ry * kRW + lane] = y[i];
+    }
+    __syncthreads();
+    const float beta = sBeta[it];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int ry = wave + kWaves * i;
+      const int j = r0 + ry;
+      const float2 down = sY[(ry < RH - 1 ? ry + 1 : RH - 1) * kRW + lane];
+      const float2 right = sY[ry * kRW + (lane < kRW - 1 ? lane + 1 : kRW - 1)];
+      const float4 g = dual_step(r[i], y[i], down, right, J.c, j < J.m - 1, has_right);
+      const float4 qn = proj_s<KIND>(g, J.R);
+      r[i] = extrapolate(qn, q[i], beta);
+      q[i] = qn;
+    }
+  }
+
+  const bool col_out = lane >= H && lane < kRW - H && kin;
+  if (J.x) {
+    // Eq. (18): x = P_C(b - lambda L^T q_K). The LDS pairs were last read in
+    // step 2 of the final iteration, which a barrier has already closed.
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int ry = wave + kWaves * i;
+      sA1[ry * kRW + lane] = make_float2(q[i].x, q[i].y);
+      sA2[ry * kRW + lane] = make_float2(q[i].z, q[i].w);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int ry = wave + kWaves * i;
+      const int j = r0 + ry;
+      if (col_out && ry >= H && ry < RH - H && j < J.m) {
+        const float2 up = (j > 0) ? sA1[(ry - 1) * kRW + lane] : zero2;
+        const float2 left = has_left ? sA2[ry * kRW + lane - 1] : zero2;
+        J.x[(long long)j * J.n + k] =
+            proj_c<CONSTR>(dual_to_primal(b[i], q[i], up, left, J.lam), inside[i]);
+      }
+    }
+  }
+  if (J.st_out) {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int ry = wave + kWaves * i;
+      const int j = r0 + ry;
+      if (col_out && ry >= H && ry < RH - H && j < J.m) {
+        const long long p = (long long)j * J.n + k;
+        J.st_out[p] = q[i];
+        J.st_out[plane + p] = r[i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain kernel: `batch` images of one shape, one parameter set.
+// ---------------------------------------------------------------------------
+template <int KIND, int CONSTR, bool MASK, int RH>
+__global__ __launch_bounds__(kThreads) void fgp_plain_kernel(FgpPlainArgs P) {
+  __shared__ float2 sA1[RH * kRW];
+  __shared__ float2 sA2[RH * kRW];
+  __shared__ float2 sY[RH * kRW];
+  __shared__ float sBeta[kMaxFuse];
+  if (threadIdx.x < kMaxFuse) sBeta[threadIdx.x] = P.beta[threadIdx.x];
+  __syncthreads();
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_img = P.tiles_x * P.tiles_y;
+  const int img = tile / per_img;
+  const int t = tile - img * per_img;
+  const long long px = (long long)P.m * P.n;
+  TileJob J;
+  J.b = reinterpret_cast<const float2*>(P.b) + img * px;
+  J.mask = P.mask;
+  J.st_in = P.st_in ? reinterpret_cast<const float4*>(P.st_in) + img * 2 * px : nullptr;
+  J.st_out = P.st_out ? reinterpret_cast<float4*>(P.st_out) + img * 2 * px : nullptr;
+  J.x = P.x ? reinterpret_cast<float2*>(P.x) + img * px : nullptr;
+  J.m = P.m;
+  J.n = P.n;
+  J.ty = t / P.tiles_x;
+  J.tx = t - J.ty * P.tiles_x;
+  J.lam = P.lam[img];
+  J.c = P.c[img];
+  J.R = P.R;
+  J.T = P.T;
+  fgp_tile<KIND, CONSTR, MASK, RH>(J, P.halo, sBeta, sA1, sA2, sY);
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernel: a tile work list over many images with their own shape,
+// lambda, kind, alpha, iteration count and mask (descriptor table).
+// ---------------------------------------------------------------------------
+template <int CONSTR, int RH>
+__global__ __launch_bounds__(kThreads) void fgp_batched_kernel(FgpBatchedArgs P) {
+  __shared__ float2 sA1[RH * kRW];
+  __shared__ float2 sA2[RH * kRW];
+  __shared__ float2 sY[RH * kRW];
+  __shared__ float sBeta[kMaxFuse];
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const BatchTile bt = P.tiles[tile];
+  const BatchImage D = P.images[bt.image];
+  const int Ti = min(P.T, D.iters - P.k0);
+  if (Ti < 0 || (Ti == 0 && D.iters != 0) || (D.iters == 0 && P.k0 != 0)) return;
+  if (threadIdx.x < kMaxFuse)
+    sBeta[threadIdx.x] = (threadIdx.x < Ti) ? P.beta_table[P.k0 + 1 + threadIdx.x] : 0.0f;
+  __syncthreads();
+  const bool last = (P.k0 + Ti == D.iters);
+  const long long px = (long long)D.m * D.n;
+  TileJob J;
+  J.b = reinterpret_cast<const float2*>(P.b) + D.offset;
+  J.mask = (D.support_offset >= 0 && P.support) ? P.support + D.support_offset : nullptr;
+  J.st_in = (P.k0 == 0) ? nullptr : reinterpret_cast<const float4*>(P.st_in) + 2 * D.offset;
+  J.st_out = last ? nullptr : reinterpret_cast<float4*>(P.st_out) + 2 * D.offset;
+  J.x = last ? reinterpret_cast<float2*>(P.x) + D.offset : nullptr;
+  J.m = D.m;
+  J.n = D.n;
+  J.tx = bt.tx;
+  J.ty = bt.ty;
+  J.lam = D.lam;
+  J.c = D.c;
+  J.R = D.R;
+  J.T = Ti;
+  const bool has_mask = J.mask != nullptr;
+  switch (D.kind * 2 + (has_mask ? 1 : 0)) {
+    case 0: fgp_tile<K1I, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+    case 1: fgp_tile<K1I, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+    case 2: fgp_tile<K1A, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+    case 3: fgp_tile<K1A, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+    case 4: fgp_tile<K2I, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+    case 5: fgp_tile<K2I, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+    case 6: fgp_tile<K2A, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+    default: fgp_tile<K2A, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Zero fill (used instead of a memset node so calls stay safe to capture).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void zero_f4_kernel(float4* __restrict__ p, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+hipError_t launch_zero_f4(float* p, long long count_f4, hipStream_t s) {
+  if (count_f4 <= 0) return hipSuccess;
+  const int nb = (int)((count_f4 + 255) / 256);
+  hipLaunchKernelGGL(zero_f4_kernel, dim3(nb), dim3(256), 0, s, reinterpret_cast<float4*>(p), count_f4);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// x = P_C(b) (lambda = 0 or K = 0).
+// ---------------------------------------------------------------------------
+template <int CONSTR>
+__global__ __launch_bounds__(256) void project_c_kernel(const float2* __restrict__ b,
+                                                        const uint8_t* __restrict__ mask,
+                                                        float2* __restrict__ x, long long px,
+                                                        long long total) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const bool in = mask ? (mask[i % px] != 0) : true;
+  x[i] = proj_c<CONSTR>(b[i], in);
+}
+
+// ---------------------------------------------------------------------------
+// Duality gap: per pixel the group term(s)
+//   ||(L x)_g||_* - <q_g, (L x)_g>  (weighted by alpha / 1-alpha for type-II),
+// nonnegative for q in S; reduced in float64, deterministically.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ double gap_term(float4 q, float2 x, float2 xd, float2 xr, bool hd,
+                                           bool hr, const Radii& R) {
+  const float u1 = hd ? x.x - xd.x : 0.0f, v1 = hd ? x.y - xd.y : 0.0f;
+  const float u2 = hr ? x.x - xr.x : 0.0f, v2 = hr ? x.y - xr.y : 0.0f;
+  const double dot = (double)q.x * u1 + (double)q.y * v1 + (double)q.z * u2 + (double)q.w * v2;
+  double nrm;
+  if (KIND == K1I) {
+    nrm = sqrt((double)u1 * u1 + (double)v1 * v1 + (double)u2 * u2 + (double)v2 * v2);
+  } else if (KIND == K1A) {
+    nrm = sqrt((double)u1 * u1 + (double)v1 * v1) + sqrt((double)u2 * u2 + (double)v2 * v2);
+  } else if (KIND == K2I) {
+    nrm = (double)R.ra * sqrt((double)u1 * u1 + (double)u2 * u2) +
+          (double)R.sa * sqrt((double)v1 * v1 + (double)v2 * v2);
+  } else {
+    nrm = (double)R.ra * (fabs((double)u1) + fabs((double)u2)) +
+          (double)R.sa * (fabs((double)v1) + fabs((double)v2));
+  }
+  return nrm - dot;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void gap_partial_kernel(const float2* __restrict__ x,
+                                                          const float4* __restrict__ st,
+                                                          int m, int n, Radii R, int blocks_per_img,
+                                                          double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int img = blockIdx.x / blocks_per_img;
+  const int blk = blockIdx.x - img * blocks_per_img;
+  const long long px = (long long)m * n;
+  const float2* xi = x + img * px;
+  const float4* qi = st + img * 2 * px;
+  double acc = 0.0;
+  for (long long p = (long long)blk * blockDim.x + threadIdx.x; p < px;
+       p += (long long)blocks_per_img * blockDim.x) {
+    const int j = (int)(p / n), k = (int)(p - (long long)j * n);
+    const bool hd = j < m - 1, hr = k < n - 1;
+    const float2 xv = xi[p];
+    const float2 xd = hd ? xi[p + n] : xv;
+    const float2 xr = hr ? xi[p + 1] : xv;
+    acc += gap_term<KIND>(qi[p], xv, xd, xr, hd, hr, R);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void gap_final_kernel(const double* __restrict__ partial, int blocks_per_img,
+                                 GapArgs L, double* __restrict__ gap, int batch) {
+  const int img = threadIdx.x;
+  if (img >= batch) return;
+  double s = 0.0;
+  for (int i = 0; i < blocks_per_img; ++i) s += partial[img * blocks_per_img + i];
+  gap[img] = (double)L.lam[img] * s;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+template <int KIND, int CONSTR, bool MASK>
+static hipError_t launch_plain_rh(const FgpPlainArgs& a, int rh, int nblocks, hipStream_t s) {
+  if (rh == 32)
+    hipLaunchKernelGGL((fgp_plain_kernel<KIND, CONSTR, MASK, 32>), dim3(nblocks), dim3(kThreads), 0, s, a);
+  else if (rh == 64)
+    hipLaunchKernelGGL((fgp_plain_kernel<KIND, CONSTR, MASK, 64>), dim3(nblocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((fgp_plain_kernel<KIND, CONSTR, MASK, 16>), dim3(nblocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t launch_plain_kind(const FgpPlainArgs& a, int constr, bool mask, int rh, int nb,
+                                    hipStream_t s) {
+  if (constr == C_MOD)
+    return mask ? launch_plain_rh<KIND, C_MOD, true>(a, rh, nb, s)
+                : launch_plain_rh<KIND, C_MOD, false>(a, rh, nb, s);
+  return mask ? launch_plain_rh<KIND, C_NONE, true>(a, rh, nb, s)
+              : launch_plain_rh<KIND, C_NONE, false>(a, rh, nb, s);
+}
+
+hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, int rh, int batch,
+                            hipStream_t s) {
+  const int nblocks = a.tiles_x * a.tiles_y * batch;
+  const bool mask = a.mask != nullptr;
+  switch (kind) {
+    case K1I: return launch_plain_kind<K1I>(a, constr, mask, rh, nblocks, s);
+    case K1A: return launch_plain_kind<K1A>(a, constr, mask, rh, nblocks, s);
+    case K2I: return launch_plain_kind<K2I>(a, constr, mask, rh, nblocks, s);
+    default: return launch_plain_kind<K2A>(a, constr, mask, rh, nblocks, s);
+  }
+}
+
+const void* fgp_batched_kernel_ptr(int constr, int rh) {
+  if (constr == C_MOD) {
+    if (rh == 32) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, 32>);
+    if (rh == 64) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, 64>);
+    return reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, 16>);
+  }
+  if (rh == 32) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, 32>);
+  if (rh == 64) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, 64>);
+  return reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, 16>);
+}
+
+hipError_t launch_fgp_batched(const FgpBatchedArgs& a, int constr, int rh, int nblocks,
+                              hipStream_t s) {
+  void* args[] = {const_cast<FgpBatchedArgs*>(&a)};
+  return hipLaunchKernel(fgp_batched_kernel_ptr(constr, rh), dim3(nblocks), dim3(kThreads), args, 0, s);
+}
+
+hipError_t launch_project_c(const float* b, const uint8_t* mask, float* x, long long px,
+                            int batch, int constr, hipStream_t s) {
+  const long long total = px * batch;
+  const int nb = (int)((total + 255) / 256);
+  if (constr == C_MOD)
+    hipLaunchKernelGGL(project_c_kernel<C_MOD>, dim3(nb), dim3(256), 0, s,
+                       reinterpret_cast<const float2*>(b), mask, reinterpret_cast<float2*>(x), px, total);
+  else
+    hipLaunchKernelGGL(project_c_kernel<C_NONE>, dim3(nb), dim3(256), 0, s,
+                       reinterpret_cast<const float2*>(b), mask, reinterpret_cast<float2*>(x), px, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_gap(const float* x, const float* state, int m, int n, int batch, int kind,
+                      Radii R, const GapArgs& lam, double* partial, int blocks_per_img,
+                      double* gap, hipStream_t s) {
+  const float2* xx = reinterpret_cast<const float2*>(x);
+  const float4* st = reinterpret_cast<const float4*>(state);
+  const int nb = blocks_per_img * batch;
+  switch (kind) {
+    case K1I: hipLaunchKernelGGL(gap_partial_kernel<K1I>, dim3(nb), dim3(256), 0, s, xx, st, m, n, R, blocks_per_img, partial); break;
+    case K1A: hipLaunchKernelGGL(gap_partial_kernel<K1A>, dim3(nb), dim3(256), 0, s, xx, st, m, n, R, blocks_per_img, partial); break;
+    case K2I: hipLaunchKernelGGL(gap_partial_kernel<K2I>, dim3(nb), dim3(256), 0, s, xx, st, m, n, R, blocks_per_img, partial); break;
+    default: hipLaunchKernelGGL(gap_partial_kernel<K2A>, dim3(nb), dim3(256), 0, s, xx, st, m, n, R, blocks_per_img, partial); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(64), 0, s, partial, blocks_per_img, lam,
+                     gap, batch);
+  return hipGetLastError();
+}
+
+}  // namespace ctv

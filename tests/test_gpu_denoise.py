@@ -1,0 +1,138 @@
+"""GPU parity of ctv_denoise against the FP64 oracle (relative L2 <= 1e-5 at
+equal iteration count), plus exact properties: special cases, determinism
+across fusion depths, resume, real inputs, conjugation, constraint set and
+mask. Calls go through the C ABI via the Python binding."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import tv
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TOL = 1e-5
+
+
+def ctv():
+    import paper_2109_05496_amd as m
+    return m
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def gpu_denoise(b, lam, **kw):
+    x = ctv().denoise(dev(b.astype(np.complex64)), lam, **kw)
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+def case(shape, seed, sigma=0.15, shapes=6):
+    rng = np.random.default_rng(seed)
+    truth, b = synth.denoise_case(shape[0], shape[1], shapes, sigma, rng)
+    return b
+
+
+def test_config1_matches_oracle():
+    c = synth.config1(0)
+    x = gpu_denoise(c["b"], c["lam"], kind="1i", iters=c["iters"])
+    xo = tv.fgp(c["b"].astype(np.complex128), c["lam"], c["iters"], "1i")
+    print("config1 rel-L2", rel(x, xo))
+    assert rel(x, xo) <= TOL
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+@pytest.mark.parametrize("constraint", ["modulus", "none"])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 67), (70, 1), (37, 53), (130, 150)])
+def test_kinds_shapes_match_oracle(kind, constraint, shape):
+    b = case(shape, 11)
+    if constraint == "modulus":
+        b = (b * 1.6).astype(np.complex64)       # many pixels outside the unit disc
+    lam, K, alpha = 0.08, 30, 0.35
+    x = gpu_denoise(b, lam, kind=kind, alpha=alpha, constraint=constraint, iters=K)
+    xo = tv.fgp(b.astype(np.complex128), lam, K, kind, alpha, constraint)
+    assert rel(x, xo) <= TOL, (kind, constraint, shape, rel(x, xo))
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_mask_matches_oracle(kind):
+    rng = np.random.default_rng(5)
+    b = case((96, 140), 3)
+    mask = synth.square_mask(96, 140, 0.7, rng)
+    x = ctv().denoise(dev(b), 0.08, kind=kind, support=dev(mask), iters=40)
+    x = x.cpu().numpy()
+    xo = tv.fgp(b.astype(np.complex128), 0.08, 40, kind, 0.5, "modulus", mask)
+    assert rel(x, xo) <= TOL
+    assert np.all(x[mask == 0] == 0)
+    assert np.all(np.abs(x) <= 1 + 1e-6)
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_fusion_depth_is_bitwise_invisible(kind):
+    b = case((150, 170), 8)
+    ref = gpu_denoise(b, 0.1, kind=kind, iters=23, fuse=1)
+    for fuse in (2, 3, 4, 7, 8, 16):
+        x = gpu_denoise(b, 0.1, kind=kind, iters=23, fuse=fuse)
+        assert np.array_equal(x.view(np.uint32), ref.view(np.uint32)), fuse
+    again = gpu_denoise(b, 0.1, kind=kind, iters=23, fuse=0)
+    assert np.array_equal(again.view(np.uint32), ref.view(np.uint32))
+
+
+def test_resume_is_bitwise_continuous():
+    b = case((90, 77), 9)
+    bt = dev(b)
+    full = ctv().denoise(bt, 0.07, kind="1a", iters=40).cpu().numpy()
+    _, st = ctv().denoise(bt, 0.07, kind="1a", iters=15, return_state=True)
+    x2 = ctv().denoise(bt, 0.07, kind="1a", iters=25, state=st, k0=15).cpu().numpy()
+    assert np.array_equal(x2.view(np.uint32), full.view(np.uint32))
+
+
+def test_lambda_zero_and_K_zero_give_projection():
+    b = (case((40, 33), 2) * 1.7).astype(np.complex64)
+    mask = (np.random.default_rng(1).random((40, 33)) > 0.3).astype(np.uint8)
+    pu, pv = tv.P_C(b.real.astype(np.float64), b.imag.astype(np.float64), "modulus", mask)
+    expect = pu + 1j * pv
+    for lam, K in ((0.0, 20), (0.3, 0)):
+        x = ctv().denoise(dev(b), lam, iters=K, support=dev(mask)).cpu().numpy()
+        np.testing.assert_allclose(x, expect, rtol=0, atol=2e-7)
+        assert np.all(x[mask == 0] == 0)
+
+
+def test_real_input_stays_real_and_conjugation_is_exact():
+    b = case((64, 80), 4)
+    br = b.real.astype(np.float32).astype(np.complex64)
+    for kind in tv.KINDS:
+        x = gpu_denoise(br, 0.1, kind=kind, iters=25)
+        assert np.all(x.imag == 0), kind
+        x = gpu_denoise(b, 0.1, kind=kind, iters=25)
+        xc = gpu_denoise(np.conj(b), 0.1, kind=kind, iters=25)
+        assert np.array_equal(xc, np.conj(x)), kind
+
+
+def test_batch_of_images_with_own_lambdas():
+    rng = np.random.default_rng(3)
+    bs = np.stack([synth.denoise_case(48, 56, 5, 0.1, rng)[1] for _ in range(35)])
+    lams = list(np.exp(rng.uniform(np.log(0.01), np.log(0.2), 35)))
+    x = ctv().denoise(dev(bs), lams, kind="2i", iters=20).cpu().numpy()
+    for i in (0, 17, 31, 32, 34):       # both sides of the 32-image launch chunk
+        xo = tv.fgp(bs[i].astype(np.complex128), lams[i], 20, "2i")
+        assert rel(x[i], xo) <= TOL, i
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_duality_gap_matches_oracle(kind):
+    b = case((50, 60), 6)
+    K = 60
+    x, g, st = ctv().denoise(dev(b), 0.1, kind=kind, iters=K, gap=True, return_state=True)
+    gpu_gap = float(g.cpu()[0])
+    _, (q, _, _) = tv.fgp(b.astype(np.complex128), 0.1, K, kind, return_state=True)
+    ora, _ = tv.gap_groups(q, b.astype(np.complex128), 0.1, kind)
+    assert gpu_gap >= -1e-6
+    assert abs(gpu_gap - ora) <= 1e-3 * abs(ora) + 1e-5, (gpu_gap, ora)
