@@ -1,0 +1,148 @@
+#!/usr/bin/env python3
+"""CTV-FGP throughput on one MI355X.
+
+Workload (one "step"): the masked 2048 x 2048 complex64 denoising problem
+(200 random disks/rectangles, noise sigma 0.15, lambda 0.08, |x| <= 1 with a
+square support covering 70 % of the pixels), solved with 200 FGP iterations for
+each of the four complex TV kinds (type-I/II, isotropic/anisotropic). Inputs
+are synthetic and seeded, resident in HBM before timing starts.
+
+Prints one JSON line: Mpixel-iterations/s over the timed steps, the roofline
+record of the dominant kernel (the fused FGP tile kernel; average launch
+duration from HIP events on the stream the kernels run on), and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+BYTES_PER_PX_IT_MASKED = 57    # read b 8 + q 16 + r 16 + mask 1, write q 16 (per pixel-iteration)
+FLOPS_PER_PX_IT = {"1i": 52, "1a": 52, "2i": 52, "2a": 44}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--iters", type=int, default=200)
+    ap.add_argument("--fuse", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=4)
+    return ap.parse_args()
+
+
+def cpu_baseline(c, sample_iters):
+    """The FP64 numpy oracle, as it stands, on a bounded sample of the same
+    workload: every kind on the full image for `sample_iters` iterations."""
+    import numpy as np
+    from oracle import tv
+    b = c["b"].astype(np.complex128)
+    n_px = b.size
+    t0 = time.perf_counter()
+    for kind in c["kinds"]:
+        tv.fgp(b, c["lam"], sample_iters, kind, c["alpha"], c["constraint"], c["mask"])
+    dt = time.perf_counter() - t0
+    work = len(c["kinds"]) * n_px * sample_iters
+    threads = int(os.environ.get("OMP_NUM_THREADS", "1") or 1)
+    return {"value": work / dt / 1e6, "unit": "Mpixel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(c['kinds'])} kinds x {sample_iters} FGP iterations on the full "
+                      f"{b.shape[0]}x{b.shape[1]} masked image ({dt:.1f} s, numpy float64, single-threaded "
+                      f"elementwise; OMP_NUM_THREADS={threads})"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(this build runs on a single MI355X; multi-GPU sharding is design-only)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2109_05496_amd as ctv
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    c = synth.config2(0, size=args.size)
+    m, n = c["b"].shape
+    K = args.iters
+    b = torch.as_tensor(c["b"]).to(dev)
+    mask = torch.as_tensor(c["mask"]).to(dev)
+    x = torch.empty_like(b)
+    ws_bytes, _ = ctv.workspace_size(m, n, 1, iters=K, fuse=args.fuse)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    kinds = list(c["kinds"])
+
+    def run_kind(kind):
+        ctv.denoise(b, c["lam"], kind=kind, alpha=c["alpha"], constraint=c["constraint"], support=mask,
+                    iters=K, fuse=args.fuse, out=x, workspace=ws)
+
+    for _ in range(args.warmup):
+        for kind in kinds:
+            run_kind(kind)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(kinds) + 1)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        for i, kind in enumerate(kinds):
+            run_kind(kind)
+            ev[s][i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_kind_ms = {k: 0.0 for k in kinds}
+    for s in range(args.steps):
+        for i, kind in enumerate(kinds):
+            per_kind_ms[kind] += ev[s][i].elapsed_time(ev[s][i + 1])
+    gpu_ms = sum(per_kind_ms.values())
+    ms_per_step = gpu_ms / args.steps
+    px_iters_step = len(kinds) * m * n * K
+    value = px_iters_step / (ms_per_step * 1e-3) / 1e6
+
+    # roofline of the dominant kernel: the fused tile kernel (one instantiation per kind)
+    from paper_2109_05496_amd import tiling
+    T, rh = tiling(args.fuse, K)
+    launches = math.ceil(K / T)
+    dom = max(kinds, key=lambda k: per_kind_ms[k])
+    avg_launch_s = per_kind_ms[dom] / args.steps / launches * 1e-3
+    alg_bytes_launch = BYTES_PER_PX_IT_MASKED * m * n * K / launches
+    achieved_gbs = alg_bytes_launch / avg_launch_s / 1e9
+    alg_flops_launch = FLOPS_PER_PX_IT[dom] * m * n * K / launches
+    achieved_tflops = alg_flops_launch / avg_launch_s / 1e12
+    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"fgp_plain_kernel<{dom}> (T={T}, 64x{rh} tiles)",
+            "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "alg_bytes_per_launch": int(alg_bytes_launch),
+            "alu_view": {"achieved": round(achieved_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}}
+
+    out = {"metric": "CTV-FGP Mpixel-iters/s & %HBM peak", "value": round(value, 1),
+           "unit": "Mpixel-iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"masked {m}x{n} complex64 CTV denoise, all four TV kinds x {K} FGP iterations",
+                      "size": [m, n], "kinds": kinds, "iters": K, "lambda": c["lam"], "alpha": c["alpha"],
+                      "constraint": "|x|<=1 + 70% square support", "fuse": T, "region_rows": rh},
+           "per_kind_ms": {k: round(v / args.steps, 3) for k, v in per_kind_ms.items()},
+           "wall_s": round(wall, 3),
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,10 @@ typedef struct {
   int32_t constraint;   /* CTV_C_* */
   int32_t iters;        /* K >= 0, FGP iterations (Algorithm 2) */
   int32_t fuse;         /* iterations fused per kernel launch, 1..16; 0 = automatic */
+  int32_t tile_waves;   /* tile shape (tuning): 0 = automatic; 4, 8 or 16 wave64s per workgroup in
+                           the column-register tile; -1 = the LDS-staged tile (4 waves) */
+  int32_t tile_rows;    /* rows per thread: 0 = automatic; column tile 4 or 8 (with waves 4: 8 only);
+                           LDS tile 4, 8 or 16 */
 } ctv_params;
 
 /* Library version (major*10000 + minor*100 + patch) and last error message. */
@@ -81,10 +85,16 @@ const char* ctv_last_error(void);
  *   ws_bytes    : scratch for ctv_denoise; ctv_denoise_backward needs
  *                 ctv_backward_workspace_size() instead.
  *   saved_bytes : size of the `saved` checkpoint buffer for ckpt_every > 0
- *                 (ceil(K / ckpt_every) dual states), else 0.
+ *                 (ceil(K / ckpt_every) - 1 dual states), else 0.
  * Either output pointer may be NULL. */
 ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
                               int32_t ckpt_every, size_t* ws_bytes, size_t* saved_bytes);
+
+/* Launch configuration ctv_denoise uses for these sizes: iterations fused per
+ * kernel launch and tile region rows (tiles are 64 columns wide). Host-only.
+ * Fails with CTV_ERR_INVALID_ARG for an unsupported tile_waves/tile_rows pair. */
+ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, int32_t* fuse_out,
+                      int32_t* region_rows_out);
 
 /* ctv_denoise - K FGP iterations (Algorithm 2) on each of `batch` equally
  * sized images followed by Eq. (18).
@@ -100,9 +110,10 @@ ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int
  *               already done; NULL = cold start q_0 = 0 (Algorithm 2, line 1), then k0 must be 0.
  *   k0          iterations already performed (t_{k0} continues the t sequence).
  *   state_out   dual state after k0 + K iterations, or NULL.
- *   ckpt_every  0, or c > 0 to store the dual state at k = 0, c, 2c, ... < K in
- *               `saved` (needed by ctv_denoise_backward); requires state_in == NULL.
- *   saved       [ceil(K/c)][batch][2][m][n][4] floats, or NULL when ckpt_every = 0.
+ *   ckpt_every  0, or c > 0 to store the dual state at k = c, 2c, ... < K in
+ *               `saved` (the state at k = 0 is the cold start); needed by
+ *               ctv_denoise_backward; requires state_in == NULL.
+ *   saved       [ceil(K/c) - 1][batch][2][m][n][4] floats, or NULL when no slot is needed.
  *   ws          workspace of at least ctv_workspace_size() bytes.
  * Errors: CTV_ERR_INVALID_ARG (null/negative/out-of-range arguments, unknown
  * kind/constraint, alpha outside [0,1], lambda < 0 or non-finite, m or n < 1,

@@ -7,8 +7,8 @@ supplies device memory and the current stream. There is no CPU fallback: if
 the library is missing, the first call raises.
 """
 from .api import (BatchedPlan, CTVDenoise, denoise, denoise_backward, fft2, phase_retrieval,
-                  pr_forward, pr_gradient, workspace_size)
+                  pr_forward, pr_gradient, tiling, workspace_size)
 from ._lib import CtvError, EXPORTS, LIB_PATH
 
-__all__ = ["denoise", "denoise_backward", "workspace_size", "BatchedPlan", "CTVDenoise",
+__all__ = ["denoise", "denoise_backward", "workspace_size", "tiling", "BatchedPlan", "CTVDenoise",
            "phase_retrieval", "pr_forward", "pr_gradient", "fft2", "CtvError", "EXPORTS", "LIB_PATH"]

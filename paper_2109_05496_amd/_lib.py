@@ -33,7 +33,8 @@ class CtvError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("struct_size", c_u32), ("tv_kind", c_i32), ("alpha", c_f),
-                ("constraint", c_i32), ("iters", c_i32), ("fuse", c_i32)]
+                ("constraint", c_i32), ("iters", c_i32), ("fuse", c_i32), ("tile_waves", c_i32),
+                ("tile_rows", c_i32)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -51,6 +52,8 @@ class PrParams(ctypes.Structure):
 _SIGS = {
     "ctv_version": (c_i32, []),
     "ctv_last_error": (ctypes.c_char_p, []),
+    "ctv_tiling": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, ctypes.POINTER(c_i32),
+                           ctypes.POINTER(c_i32)]),
     "ctv_workspace_size": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_i32, c_psz, c_psz]),
     "ctv_denoise": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_f), c_vp,
                             c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_sz, c_vp]),
@@ -99,10 +102,10 @@ def call(name, *args):
     check(name, getattr(lib(), name)(*args))
 
 
-def make_params(kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0):
+def make_params(kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0, tile=(0, 0)):
     if kind not in KINDS:
         raise ValueError(f"unknown TV kind {kind!r}")
     if constraint not in CONSTRAINTS:
         raise ValueError(f"unknown constraint {constraint!r}")
     return Params(ctypes.sizeof(Params), KINDS[kind], float(alpha), CONSTRAINTS[constraint], int(iters),
-                  int(fuse))
+                  int(fuse), int(tile[0]), int(tile[1]))

@@ -38,6 +38,14 @@ def _lams(lam, batch):
     return (ctypes.c_float * batch)(*lam)
 
 
+def tiling(fuse=0, iters=100, m=2048, n=2048, batch=1, tile=(0, 0)):
+    """(iterations fused per launch, tile region rows) that ctv_denoise uses."""
+    p = make_params("1i", 0.5, "modulus", iters, fuse, tile)
+    t, r = ctypes.c_int32(), ctypes.c_int32()
+    call("ctv_tiling", ctypes.byref(p), batch, m, n, ctypes.byref(t), ctypes.byref(r))
+    return t.value, r.value
+
+
 def workspace_size(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0,
                    ckpt_every=0):
     """(workspace bytes, checkpoint bytes) for ``denoise``."""
@@ -49,7 +57,7 @@ def workspace_size(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", it
 
 def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, iters=100, fuse=0,
             gap=False, state=None, k0=0, return_state=False, ckpt_every=0, saved=None, out=None,
-            workspace=None):
+            workspace=None, tile=(0, 0)):
     """K FGP iterations (Algorithm 2) + Eq. (18) on the GPU.
 
     b: complex64 CUDA tensor [m, n] or [B, m, n]. lam: float or B floats.
@@ -61,7 +69,7 @@ def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, it
     bb = b.unsqueeze(0) if squeeze else b
     B, m, n = bb.shape
     dev = bb.device
-    p = make_params(kind, alpha, constraint, iters, fuse)
+    p = make_params(kind, alpha, constraint, iters, fuse, tile)
     if support is not None:
         _require_cuda(support, "support", torch.uint8)
         if tuple(support.shape) != (m, n):

@@ -76,18 +76,37 @@ float step_of(float lam) {
   return lam > 0.0f ? (float)(1.0 / (8.0 * (double)lam)) : 0.0f;
 }
 
-Tiling choose_tiling(int fuse, int iters, int m, int n, int batch) {
+bool valid_tile_shape(const TileShape& ts) {
+  if (ts.waves > 0)
+    return (ts.waves == 4 && ts.rows_per_thread == 8) ||
+           ((ts.waves == 8 || ts.waves == 16) && (ts.rows_per_thread == 4 || ts.rows_per_thread == 8));
+  return ts.rows_per_thread == 4 || ts.rows_per_thread == 8 || ts.rows_per_thread == 16;
+}
+
+ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out) {
   (void)m;
   (void)n;
   (void)batch;
   Tiling t;
-  t.T = fuse > 0 ? fuse : 4;
-  if (iters > 0) t.T = std::min(t.T, iters);
+  t.shape.waves = 8;
+  t.shape.rows_per_thread = 8;
+  if (p->tile_waves != 0 || p->tile_rows != 0) {
+    if (p->tile_waves == 0 || p->tile_rows == 0) return fail(CTV_ERR_INVALID_ARG, "tile_waves and tile_rows must be set together");
+    t.shape.waves = p->tile_waves < 0 ? 0 : p->tile_waves;
+    t.shape.rows_per_thread = p->tile_rows;
+    if (p->tile_waves < -1 || !valid_tile_shape(t.shape)) return fail(CTV_ERR_INVALID_ARG, "unsupported tile shape");
+  }
+  // halo H <= (min(64, rows) - 1) / 2 keeps at least one output row and column;
+  // the epilogue launch needs H = T + 1.
+  const int hmax = (std::min(64, t.shape.rows()) - 1) / 2;
+  // Default from the tiling sweep on MI355X (2048^2, K = 200): 8 waves x 8 rows
+  // (64 x 64 regions) with 8 fused iterations.
+  t.T = p->fuse > 0 ? p->fuse : 8;
+  t.T = std::min(t.T, hmax - 1);
+  if (p->iters > 0) t.T = std::min(t.T, p->iters);
   t.T = std::max(t.T, 1);
-  // the epilogue launch needs a halo of T + 1 and at least one output row
-  t.rh = (2 * (t.T + 1) + 8 <= 32) ? 32 : 64;
-  if (fuse == 0) t.rh = 64;
-  return t;
+  *out = t;
+  return CTV_OK;
 }
 
 size_t state_bytes(long long batch, long long m, long long n) { return (size_t)(batch * 2 * m * n * 16); }
@@ -130,6 +149,19 @@ ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int
   return CTV_OK;
 }
 
+ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, int32_t* fuse_out,
+                      int32_t* region_rows_out) {
+  ctv_status st = validate_params(p);
+  if (st) return st;
+  if (batch < 1 || m < 1 || n < 1) return fail(CTV_ERR_INVALID_ARG, "batch, m and n must be >= 1");
+  Tiling t;
+  st = choose_tiling(p, m, n, batch, &t);
+  if (st) return st;
+  if (fuse_out) *fuse_out = t.T;
+  if (region_rows_out) *region_rows_out = t.shape.rows();
+  return CTV_OK;
+}
+
 ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n, const float* b,
                        const float* lambda_host, const uint8_t* support, float* x, double* gap,
                        const float* state_in, int32_t k0, float* state_out, int32_t ckpt_every,
@@ -162,7 +194,9 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
   float* bufA = reinterpret_cast<float*>(wsb);
   float* bufB = reinterpret_cast<float*>(wsb + align_up(st_full));
   double* partial = reinterpret_cast<double*>(wsb + 2 * align_up(st_full));
-  const Tiling tl = choose_tiling(p->fuse, p->iters, m, n, batch);
+  Tiling tl;
+  st = choose_tiling(p, m, n, batch, &tl);
+  if (st) return st;
   std::vector<float> beta;
   momentum_table(k0 + p->iters + 1, beta);
   const Radii R = make_radii(p->tv_kind, p->alpha);
@@ -205,8 +239,9 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
       a.halo = std::max(a.halo, 1);
       for (int i = 0; i < kMaxFuse; ++i) a.beta[i] = (i < Tl) ? beta[(size_t)(k + 1 + i)] : 0.0f;
       a.tiles_x = (int)((n + (64 - 2 * a.halo) - 1) / (64 - 2 * a.halo));
-      a.tiles_y = (int)((m + (tl.rh - 2 * a.halo) - 1) / (tl.rh - 2 * a.halo));
-      hipError_t e = launch_fgp_plain(a, p->tv_kind, p->constraint, tl.rh, cb, s);
+      const int rows = tl.shape.rows();
+      a.tiles_y = (int)((m + (rows - 2 * a.halo) - 1) / (rows - 2 * a.halo));
+      hipError_t e = launch_fgp_plain(a, p->tv_kind, p->constraint, tl.shape, cb, s);
       if (e != hipSuccess) return hip_fail(e, "fgp launch");
       src = dst;
       k += Tl;

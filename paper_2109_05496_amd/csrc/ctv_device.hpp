@@ -16,20 +16,27 @@
 
 namespace ctv {
 
+// Hardware reciprocal square root (v_rsq_f32, ~1 ulp). Its arguments here are
+// sums of squares: a denormal argument is read as 0 and gives +inf, which the
+// callers' min(1, .) maps to a unit scale - the right answer for a vector that
+// small.
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // P_C of one pixel: x / max{1, |x|} (Eq. 26) when the modulus constraint is
-// on, then forced to 0 outside the support.
+// on, then forced to 0 outside the support (a zero scale, so masked pixels hold
+// exactly +-0).
 template <int CONSTR>
 __device__ __forceinline__ float2 proj_c(float2 w, bool inside) {
   float2 y = w;
   if (CONSTR == C_MOD) {
     const float n2 = fmaf(w.x, w.x, w.y * w.y);
-    const float s = (n2 > 1.0f) ? rsqrtf(n2) : 1.0f;
+    float s = fminf(1.0f, rsq(n2));  // 1/max{1,|w|}; rsqrt(0) = inf gives 1
+    s = inside ? s : 0.0f;
     y.x = w.x * s;
     y.y = w.y * s;
-  }
-  if (!inside) {
-    y.x = 0.0f;
-    y.y = 0.0f;
+  } else {
+    y.x = inside ? w.x : 0.0f;
+    y.y = inside ? w.y : 0.0f;
   }
   return y;
 }
@@ -39,25 +46,26 @@ __device__ __forceinline__ float2 proj_c(float2 w, bool inside) {
 //   1a: each complex direction pair onto the unit disc (Eq. 33)
 //   2i: (r1, r2) onto the alpha-disc, (s1, s2) onto the (1-alpha)-disc (Eq. 35)
 //   2a: each real entry clipped to [-alpha, alpha] or [-(1-alpha), 1-alpha] (Eq. 37)
-// A vector is scaled only when its squared norm exceeds the squared radius;
-// ties return the input, which equals the scaled value.
+// Each scale is min(1, radius / norm), i.e. the paper's radius / max{radius, norm}.
 template <int KIND>
 __device__ __forceinline__ float4 proj_s(float4 g, const Radii& R) {
   if (KIND == K1I) {
     const float n2 = fmaf(g.x, g.x, fmaf(g.y, g.y, fmaf(g.z, g.z, g.w * g.w)));
-    const float s = (n2 > 1.0f) ? rsqrtf(n2) : 1.0f;
+    const float s = fminf(1.0f, rsq(n2));
     return make_float4(g.x * s, g.y * s, g.z * s, g.w * s);
   } else if (KIND == K1A) {
     const float n1 = fmaf(g.x, g.x, g.y * g.y);
     const float n2 = fmaf(g.z, g.z, g.w * g.w);
-    const float s1 = (n1 > 1.0f) ? rsqrtf(n1) : 1.0f;
-    const float s2 = (n2 > 1.0f) ? rsqrtf(n2) : 1.0f;
+    const float s1 = fminf(1.0f, rsq(n1));
+    const float s2 = fminf(1.0f, rsq(n2));
     return make_float4(g.x * s1, g.y * s1, g.z * s2, g.w * s2);
   } else if (KIND == K2I) {
+    // rho / max{rho, ||v||} = min(1, rho / ||v||); a zero radius gives 0 * inf = NaN
+    // at v = 0, which fminf turns into 1, and 0 * v = 0 either way.
     const float nr = fmaf(g.x, g.x, g.z * g.z);
     const float ns = fmaf(g.y, g.y, g.w * g.w);
-    const float fr = (nr > R.ra2) ? R.ra * rsqrtf(nr) : 1.0f;
-    const float fs = (ns > R.sa2) ? R.sa * rsqrtf(ns) : 1.0f;
+    const float fr = fminf(1.0f, R.ra * rsq(nr));
+    const float fs = fminf(1.0f, R.sa * rsq(ns));
     return make_float4(g.x * fr, g.y * fs, g.z * fr, g.w * fs);
   } else {
     return make_float4(fminf(fmaxf(g.x, -R.ra), R.ra), fminf(fmaxf(g.y, -R.sa), R.sa),

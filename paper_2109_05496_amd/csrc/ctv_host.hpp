@@ -6,13 +6,14 @@
 #include <vector>
 
 #include "ctv.h"
+#include "ctv_kernels.hpp"
 #include "ctv_types.hpp"
 
 namespace ctv {
 
 struct Tiling {
-  int T;   // iterations fused per launch
-  int rh;  // tile region rows (64 columns)
+  int T;            // iterations fused per launch
+  TileShape shape;  // tile kernel variant and region rows (64 columns)
 };
 
 ctv_status fail(ctv_status st, const std::string& msg);
@@ -22,7 +23,7 @@ ctv_status validate_lambda(float lam);
 Radii make_radii(int kind, float alpha);
 void momentum_table(int kmax, std::vector<float>& beta);
 float step_of(float lam);
-Tiling choose_tiling(int fuse, int iters, int m, int n, int batch);
+ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out);
 size_t state_bytes(long long batch, long long m, long long n);
 int gap_blocks_per_image(long long px);
 size_t denoise_ws_bytes(int batch, int m, int n);

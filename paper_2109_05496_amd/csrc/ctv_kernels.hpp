@@ -53,10 +53,17 @@ struct FgpBatchedArgs {
   int halo;
 };
 
-// Region rows supported by the tile kernels (64 columns each).
-inline bool valid_region_rows(int rh) { return rh == 16 || rh == 32 || rh == 64; }
+// Tile shape of the plain kernels: waves > 0 selects the column-register tile
+// (waves wave64s, rows_per_thread consecutive rows each); waves == 0 selects the
+// LDS tile with 4 waves and rows_per_thread * 4 region rows.
+struct TileShape {
+  int waves;
+  int rows_per_thread;
+  int rows() const { return (waves > 0 ? waves : 4) * rows_per_thread; }
+};
+bool valid_tile_shape(const TileShape& ts);
 
-hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, int rh, int batch,
+hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const TileShape& ts, int batch,
                             hipStream_t s);
 const void* fgp_batched_kernel_ptr(int constr, int rh);
 hipError_t launch_fgp_batched(const FgpBatchedArgs& a, int constr, int rh, int nblocks,

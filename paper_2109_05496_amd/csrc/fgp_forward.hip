@@ -147,6 +147,186 @@ __device__ __forceinline__ void fgp_tile(const TileJob& J, const int H, const fl
 }
 
 // ---------------------------------------------------------------------------
+// Column-register tile. A workgroup of NW wave64s owns 64 columns x NW*P rows;
+// lane l holds column l and wave w the P consecutive rows [w*P, (w+1)*P).
+// Vertical neighbours are in the thread's own registers; horizontal ones come
+// from the adjacent lane through DPP whole-wave shifts; only the rows at the
+// boundary between two waves go through LDS (one row of (r1,s1) down, one row
+// of y up per iteration). Same arithmetic, same halo rule as above.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float lane_from_left(float v) {   // lane i <- lane i-1 (lane 0 <- 0)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_from_right(float v) {  // lane i <- lane i+1 (lane 63 <- 0)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// BORDER = false is the fast path for tiles whose region lies at least one
+// pixel inside the image on every side: no neighbour there leaves the image, so
+// the boundary selects disappear. Rows are skipped once they fall outside the
+// part of the region that can still reach the output (the shrinking trapezoid
+// of the fused iterations); one row more than the q rows needs y.
+template <int KIND, int CONSTR, bool MASK, int NW, int P, bool BORDER>
+__device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, const float* sBeta,
+                                             float2* __restrict__ sBot, float2* __restrict__ sTop) {
+  constexpr int RH = NW * P;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int OW = kRW - 2 * H, OH = RH - 2 * H;
+  const int c0 = J.tx * OW - H, r0 = J.ty * OH - H;
+  const int k = c0 + lane;
+  const int jb = r0 + wave * P;
+  const bool kin = !BORDER || ((k >= 0) && (k < J.n));
+  const bool has_left = !BORDER || k > 0;
+  const bool has_right = !BORDER || k < J.n - 1;
+  const long long plane = (long long)J.m * J.n;
+  const float2 zero2 = make_float2(0.0f, 0.0f);
+
+  float4 q[P], r[P];
+  float2 b[P];
+  bool inside[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int j = jb + i;
+    const bool in = kin && (!BORDER || (j >= 0 && j < J.m));
+    q[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    r[i] = q[i];
+    b[i] = zero2;
+    inside[i] = !BORDER;
+    if (in) {
+      const long long p = (long long)j * J.n + k;
+      b[i] = J.b[p];
+      if (J.st_in) {
+        q[i] = J.st_in[p];
+        r[i] = J.st_in[plane + p];
+      }
+      inside[i] = MASK ? (J.mask[p] != 0) : true;
+    }
+  }
+
+  // Rows whose q can still reach the output: after the last iteration the
+  // stored state needs rows [H, RH-H) and Eq. (18) additionally reads q one row
+  // up, so at iteration t the needed rows are [t + eu, RH - t - ed).
+  const int ed = H - J.T;
+  const int eu = ed - (J.x ? 1 : 0);
+  float2 y[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) y[i] = zero2;
+  for (int it = 0; it < J.T; ++it) {
+    const int lo = it + 1 + eu, hi = RH - (it + 1) - ed;
+    sBot[wave * kRW + lane] = make_float2(r[P - 1].x, r[P - 1].y);
+    __syncthreads();
+    const float2 up_lds = sBot[(wave > 0 ? wave - 1 : 0) * kRW + lane];
+    const float2 up0 = (wave > 0) ? up_lds : zero2;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int ry = wave * P + i;
+      if (ry >= lo && ry <= hi) {
+        const int j = jb + i;
+        const float lx = lane_from_left(r[i].z), ly = lane_from_left(r[i].w);
+        float2 up = (i > 0) ? make_float2(r[i - 1].x, r[i - 1].y) : up0;
+        float2 left = make_float2(lx, ly);
+        if (BORDER) {
+          up = (j > 0) ? up : zero2;
+          left = has_left ? left : zero2;
+        }
+        y[i] = proj_c<CONSTR>(dual_to_primal(b[i], r[i], up, left, J.lam), inside[i]);
+      }
+    }
+    sTop[wave * kRW + lane] = y[0];
+    __syncthreads();
+    const float2 down_lds = sTop[(wave < NW - 1 ? wave + 1 : wave) * kRW + lane];
+    const float2 down_last = (wave < NW - 1) ? down_lds : y[P - 1];
+    const float beta = sBeta[it];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int ry = wave * P + i;
+      if (ry >= lo && ry < hi) {
+        const int j = jb + i;
+        const float rx = lane_from_right(y[i].x), rv = lane_from_right(y[i].y);
+        const float2 down = (i < P - 1) ? y[i + 1] : down_last;
+        const float4 g = dual_step(r[i], y[i], down, make_float2(rx, rv), J.c,
+                                   !BORDER || j < J.m - 1, has_right);
+        const float4 qn = proj_s<KIND>(g, J.R);
+        r[i] = extrapolate(qn, q[i], beta);
+        q[i] = qn;
+      }
+    }
+  }
+
+  const bool col_out = lane >= H && lane < kRW - H && kin;
+  if (J.x) {
+    sBot[wave * kRW + lane] = make_float2(q[P - 1].x, q[P - 1].y);
+    __syncthreads();
+    const float2 up_lds = sBot[(wave > 0 ? wave - 1 : 0) * kRW + lane];
+    const float2 up0 = (wave > 0) ? up_lds : zero2;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int j = jb + i;
+      const int ry = wave * P + i;
+      if (ry >= H && ry < RH - H) {
+        const float lx = lane_from_left(q[i].z), ly = lane_from_left(q[i].w);
+        float2 up = (i > 0) ? make_float2(q[i - 1].x, q[i - 1].y) : up0;
+        float2 left = make_float2(lx, ly);
+        if (BORDER) {
+          up = (j > 0) ? up : zero2;
+          left = has_left ? left : zero2;
+        }
+        const float2 xv = proj_c<CONSTR>(dual_to_primal(b[i], q[i], up, left, J.lam), inside[i]);
+        if (col_out && (!BORDER || j < J.m)) J.x[(long long)j * J.n + k] = xv;
+      }
+    }
+  }
+  if (J.st_out) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int j = jb + i;
+      const int ry = wave * P + i;
+      if (col_out && ry >= H && ry < RH - H && (!BORDER || j < J.m)) {
+        const long long p = (long long)j * J.n + k;
+        J.st_out[p] = q[i];
+        J.st_out[plane + p] = r[i];
+      }
+    }
+  }
+}
+
+template <int KIND, int CONSTR, bool MASK, int NW, int P>
+__global__ __launch_bounds__(NW * 64) void fgp_col_kernel(FgpPlainArgs P_) {
+  __shared__ float2 sBot[NW * kRW];
+  __shared__ float2 sTop[NW * kRW];
+  __shared__ float sBeta[kMaxFuse];
+  if (threadIdx.x < kMaxFuse) sBeta[threadIdx.x] = P_.beta[threadIdx.x];
+  __syncthreads();
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_img = P_.tiles_x * P_.tiles_y;
+  const int img = tile / per_img;
+  const int t = tile - img * per_img;
+  const long long px = (long long)P_.m * P_.n;
+  TileJob J;
+  J.b = reinterpret_cast<const float2*>(P_.b) + img * px;
+  J.mask = P_.mask;
+  J.st_in = P_.st_in ? reinterpret_cast<const float4*>(P_.st_in) + img * 2 * px : nullptr;
+  J.st_out = P_.st_out ? reinterpret_cast<float4*>(P_.st_out) + img * 2 * px : nullptr;
+  J.x = P_.x ? reinterpret_cast<float2*>(P_.x) + img * px : nullptr;
+  J.m = P_.m;
+  J.n = P_.n;
+  J.ty = t / P_.tiles_x;
+  J.tx = t - J.ty * P_.tiles_x;
+  J.lam = P_.lam[img];
+  J.c = P_.c[img];
+  J.R = P_.R;
+  J.T = P_.T;
+  const int H = P_.halo;
+  const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (NW * P - 2 * H) - H;
+  const bool interior = c0 >= 1 && c0 + kRW <= J.n - 1 && r0 >= 1 && r0 + NW * P <= J.m - 1;
+  if (interior)
+    fgp_tile_col<KIND, CONSTR, MASK, NW, P, false>(J, H, sBeta, sBot, sTop);
+  else
+    fgp_tile_col<KIND, CONSTR, MASK, NW, P, true>(J, H, sBeta, sBot, sTop);
+}
+
+// ---------------------------------------------------------------------------
 // Plain kernel: `batch` images of one shape, one parameter set.
 // ---------------------------------------------------------------------------
 template <int KIND, int CONSTR, bool MASK, int RH>
@@ -351,10 +531,45 @@ static hipError_t launch_plain_kind(const FgpPlainArgs& a, int constr, bool mask
               : launch_plain_rh<KIND, C_NONE, false>(a, rh, nb, s);
 }
 
-hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, int rh, int batch,
+template <int KIND, int CONSTR, bool MASK>
+static hipError_t launch_col_shape(const FgpPlainArgs& a, int nw, int p, int nb, hipStream_t s) {
+#define CTV_COL(NW_, P_)                                                                        \
+  if (nw == NW_ && p == P_) {                                                                   \
+    hipLaunchKernelGGL((fgp_col_kernel<KIND, CONSTR, MASK, NW_, P_>), dim3(nb), dim3(NW_ * 64), 0, s, a); \
+    return hipGetLastError();                                                                   \
+  }
+  CTV_COL(4, 8)
+  CTV_COL(8, 4)
+  CTV_COL(8, 8)
+  CTV_COL(16, 4)
+  CTV_COL(16, 8)
+#undef CTV_COL
+  return hipErrorInvalidValue;
+}
+
+template <int KIND>
+static hipError_t launch_col_kind(const FgpPlainArgs& a, int constr, bool mask, int nw, int p, int nb,
+                                  hipStream_t s) {
+  if (constr == C_MOD)
+    return mask ? launch_col_shape<KIND, C_MOD, true>(a, nw, p, nb, s)
+                : launch_col_shape<KIND, C_MOD, false>(a, nw, p, nb, s);
+  return mask ? launch_col_shape<KIND, C_NONE, true>(a, nw, p, nb, s)
+              : launch_col_shape<KIND, C_NONE, false>(a, nw, p, nb, s);
+}
+
+hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const TileShape& ts, int batch,
                             hipStream_t s) {
   const int nblocks = a.tiles_x * a.tiles_y * batch;
   const bool mask = a.mask != nullptr;
+  if (ts.waves > 0) {
+    switch (kind) {
+      case K1I: return launch_col_kind<K1I>(a, constr, mask, ts.waves, ts.rows_per_thread, nblocks, s);
+      case K1A: return launch_col_kind<K1A>(a, constr, mask, ts.waves, ts.rows_per_thread, nblocks, s);
+      case K2I: return launch_col_kind<K2I>(a, constr, mask, ts.waves, ts.rows_per_thread, nblocks, s);
+      default: return launch_col_kind<K2A>(a, constr, mask, ts.waves, ts.rows_per_thread, nblocks, s);
+    }
+  }
+  const int rh = ts.rows_per_thread * kWaves;
   switch (kind) {
     case K1I: return launch_plain_kind<K1I>(a, constr, mask, rh, nblocks, s);
     case K1A: return launch_plain_kind<K1A>(a, constr, mask, rh, nblocks, s);

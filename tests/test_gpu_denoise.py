@@ -12,7 +12,11 @@ torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
-TOL = 1e-5
+TOL = 1e-5      # the stated bar: relative L2 vs the FP64 oracle at equal K
+# Regression guard: a float32 emulation of the kernels' arithmetic (same
+# operation order, 1-ulp reciprocal square roots) lands near 5e-8 on these
+# small cases, so anything above 1e-6 is a defect rather than rounding.
+GUARD = 1e-6
 
 
 def ctv():
@@ -46,6 +50,7 @@ def test_config1_matches_oracle():
     xo = tv.fgp(c["b"].astype(np.complex128), c["lam"], c["iters"], "1i")
     print("config1 rel-L2", rel(x, xo))
     assert rel(x, xo) <= TOL
+    assert rel(x, xo) <= GUARD
 
 
 @pytest.mark.parametrize("kind", tv.KINDS)
@@ -59,6 +64,7 @@ def test_kinds_shapes_match_oracle(kind, constraint, shape):
     x = gpu_denoise(b, lam, kind=kind, alpha=alpha, constraint=constraint, iters=K)
     xo = tv.fgp(b.astype(np.complex128), lam, K, kind, alpha, constraint)
     assert rel(x, xo) <= TOL, (kind, constraint, shape, rel(x, xo))
+    assert rel(x, xo) <= GUARD, (kind, constraint, shape, rel(x, xo))
 
 
 @pytest.mark.parametrize("kind", tv.KINDS)
@@ -70,6 +76,7 @@ def test_mask_matches_oracle(kind):
     x = x.cpu().numpy()
     xo = tv.fgp(b.astype(np.complex128), 0.08, 40, kind, 0.5, "modulus", mask)
     assert rel(x, xo) <= TOL
+    assert rel(x, xo) <= GUARD
     assert np.all(x[mask == 0] == 0)
     assert np.all(np.abs(x) <= 1 + 1e-6)
 
@@ -136,3 +143,23 @@ def test_duality_gap_matches_oracle(kind):
     ora, _ = tv.gap_groups(q, b.astype(np.complex128), 0.1, kind)
     assert gpu_gap >= -1e-6
     assert abs(gpu_gap - ora) <= 1e-3 * abs(ora) + 1e-5, (gpu_gap, ora)
+
+
+SHAPES = [(-1, 4), (-1, 8), (-1, 16), (4, 8), (8, 4), (8, 8), (16, 4), (16, 8)]
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_tile_shapes_are_bitwise_invisible(kind):
+    """Every tile kernel variant performs the same per-pixel float32 operations,
+    so the LDS tile and the column-register tiles agree bit for bit."""
+    rng = np.random.default_rng(21)
+    b = case((203, 141), 12)
+    mask = synth.square_mask(203, 141, 0.6, rng)
+    ref = ctv().denoise(dev(b), 0.09, kind=kind, iters=17, fuse=1, support=dev(mask), tile=(-1, 8)).cpu().numpy()
+    for tile in SHAPES:
+        for fuse in (3, 5):
+            x = ctv().denoise(dev(b), 0.09, kind=kind, iters=17, fuse=fuse, support=dev(mask), tile=tile)
+            x = x.cpu().numpy()
+            assert np.array_equal(x.view(np.uint32), ref.view(np.uint32)), (tile, fuse)
+    xo = tv.fgp(b.astype(np.complex128), 0.09, 17, kind, 0.5, "modulus", mask)
+    assert rel(ref, xo) <= TOL
