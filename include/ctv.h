@@ -91,10 +91,12 @@ ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int
                               int32_t ckpt_every, size_t* ws_bytes, size_t* saved_bytes);
 
 /* Launch configuration ctv_denoise uses for these sizes: iterations fused per
- * kernel launch and tile region rows (tiles are 64 columns wide). Host-only.
+ * kernel launch, tile region rows (tiles are 64 columns wide) and the tile
+ * shape in ctv_params' tile_waves / tile_rows terms. Host-only; any output
+ * pointer may be NULL.
  * Fails with CTV_ERR_INVALID_ARG for an unsupported tile_waves/tile_rows pair. */
 ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, int32_t* fuse_out,
-                      int32_t* region_rows_out);
+                      int32_t* region_rows_out, int32_t* tile_waves_out, int32_t* tile_rows_out);
 
 /* ctv_denoise - K FGP iterations (Algorithm 2) on each of `batch` equally
  * sized images followed by Eq. (18).

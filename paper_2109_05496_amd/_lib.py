@@ -53,7 +53,7 @@ _SIGS = {
     "ctv_version": (c_i32, []),
     "ctv_last_error": (ctypes.c_char_p, []),
     "ctv_tiling": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, ctypes.POINTER(c_i32),
-                           ctypes.POINTER(c_i32)]),
+                           ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "ctv_workspace_size": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_i32, c_psz, c_psz]),
     "ctv_denoise": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_f), c_vp,
                             c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_sz, c_vp]),

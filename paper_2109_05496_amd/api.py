@@ -38,12 +38,14 @@ def _lams(lam, batch):
     return (ctypes.c_float * batch)(*lam)
 
 
-def tiling(fuse=0, iters=100, m=2048, n=2048, batch=1, tile=(0, 0)):
-    """(iterations fused per launch, tile region rows) that ctv_denoise uses."""
+def tiling(fuse=0, iters=100, m=2048, n=2048, batch=1, tile=(0, 0), detail=False):
+    """(iterations fused per launch, tile region rows) that ctv_denoise uses;
+    with detail=True also (tile_waves, rows_per_thread)."""
     p = make_params("1i", 0.5, "modulus", iters, fuse, tile)
-    t, r = ctypes.c_int32(), ctypes.c_int32()
-    call("ctv_tiling", ctypes.byref(p), batch, m, n, ctypes.byref(t), ctypes.byref(r))
-    return t.value, r.value
+    t, r, w, rp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    call("ctv_tiling", ctypes.byref(p), batch, m, n, ctypes.byref(t), ctypes.byref(r), ctypes.byref(w),
+         ctypes.byref(rp))
+    return (t.value, r.value, w.value, rp.value) if detail else (t.value, r.value)
 
 
 def workspace_size(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0,

@@ -150,7 +150,7 @@ ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int
 }
 
 ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, int32_t* fuse_out,
-                      int32_t* region_rows_out) {
+                      int32_t* region_rows_out, int32_t* tile_waves_out, int32_t* tile_rows_out) {
   ctv_status st = validate_params(p);
   if (st) return st;
   if (batch < 1 || m < 1 || n < 1) return fail(CTV_ERR_INVALID_ARG, "batch, m and n must be >= 1");
@@ -159,6 +159,8 @@ ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, 
   if (st) return st;
   if (fuse_out) *fuse_out = t.T;
   if (region_rows_out) *region_rows_out = t.shape.rows();
+  if (tile_waves_out) *tile_waves_out = t.shape.waves > 0 ? t.shape.waves : -1;
+  if (tile_rows_out) *tile_rows_out = t.shape.rows_per_thread;
   return CTV_OK;
 }
 
