@@ -203,6 +203,15 @@ class BatchedPlan:
             flat[o:o + m * n] = torch.as_tensor(im).reshape(-1).to(device=device, dtype=torch.complex64)
         return flat
 
+    def pack_support(self, masks, device="cuda"):
+        """Packs the masks of the images declared with has_support (in order)."""
+        flat = torch.zeros(max(self.support_bytes, 1), dtype=torch.uint8, device=device)
+        it = iter(masks)
+        for so, (m, n) in zip(self.support_offsets, self.shapes):
+            if so >= 0:
+                flat[so:so + m * n] = torch.as_tensor(next(it)).reshape(-1).to(device=device, dtype=torch.uint8)
+        return flat
+
     def unpack(self, flat):
         return [flat[o:o + m * n].reshape(m, n) for o, (m, n) in zip(self.offsets, self.shapes)]
 

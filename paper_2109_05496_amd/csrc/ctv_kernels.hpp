@@ -40,7 +40,8 @@ struct BatchTile {
 };
 
 struct FgpBatchedArgs {
-  const BatchTile* tiles;
+  const BatchTile* tiles;   // this step's tiles
+  int ntiles;
   const BatchImage* images;
   const float* beta_table;  // beta_table[k] = (t_k - 1)/t_{k+1}, k >= 1
   const float* b;
@@ -48,9 +49,8 @@ struct FgpBatchedArgs {
   const float* st_in;       // packed [2 * pixels][4] per image at 2 * offset
   float* st_out;
   float* x;
-  int k0;                   // iterations completed before this launch
-  int T;                    // iterations fused in this launch
-  int halo;
+  int k0;                   // iterations completed before this step
+  int T;                    // iterations fused in this step
 };
 
 // Tile shape of the plain kernels: waves > 0 selects the column-register tile
@@ -62,12 +62,12 @@ struct TileShape {
   int rows() const { return (waves > 0 ? waves : 4) * rows_per_thread; }
 };
 bool valid_tile_shape(const TileShape& ts);
+// Batched kernel for a column-register tile shape (8x8, 8x4 or 16x4), else nullptr.
+const void* fgp_batched_kernel_ptr(int constr, const TileShape& ts);
 
 hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const TileShape& ts, int batch,
                             hipStream_t s);
-const void* fgp_batched_kernel_ptr(int constr, int rh);
-hipError_t launch_fgp_batched(const FgpBatchedArgs& a, int constr, int rh, int nblocks,
-                              hipStream_t s);
+
 hipError_t launch_zero_f4(float* p, long long count_f4, hipStream_t s);
 hipError_t launch_project_c(const float* b, const uint8_t* mask, float* x, long long px, int batch,
                             int constr, hipStream_t s);

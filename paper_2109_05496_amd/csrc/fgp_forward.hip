@@ -360,49 +360,62 @@ __global__ __launch_bounds__(kThreads) void fgp_plain_kernel(FgpPlainArgs P) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched kernel: a tile work list over many images with their own shape,
-// lambda, kind, alpha, iteration count and mask (descriptor table).
+// Batched kernel: one fused step (iterations k0+1 .. k0+T) for every image of a
+// ragged batch. The tile list of the step holds, per image still running, the
+// tiles laid out for that image's own halo (T_i + 1 when its last iteration
+// falls in this step, else T_i), so each image is computed exactly as a plain
+// call would. Persistent grid: each XCD owns one contiguous slice of the tile
+// list and its workgroups stride through it.
 // ---------------------------------------------------------------------------
-template <int CONSTR, int RH>
-__global__ __launch_bounds__(kThreads) void fgp_batched_kernel(FgpBatchedArgs P) {
-  __shared__ float2 sA1[RH * kRW];
-  __shared__ float2 sA2[RH * kRW];
-  __shared__ float2 sY[RH * kRW];
+template <int CONSTR, int NW, int P>
+__global__ __launch_bounds__(NW * 64) void fgp_batched_kernel(FgpBatchedArgs A) {
+  __shared__ float2 sBot[NW * kRW];
+  __shared__ float2 sTop[NW * kRW];
   __shared__ float sBeta[kMaxFuse];
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const BatchTile bt = P.tiles[tile];
-  const BatchImage D = P.images[bt.image];
-  const int Ti = min(P.T, D.iters - P.k0);
-  if (Ti < 0 || (Ti == 0 && D.iters != 0) || (D.iters == 0 && P.k0 != 0)) return;
-  if (threadIdx.x < kMaxFuse)
-    sBeta[threadIdx.x] = (threadIdx.x < Ti) ? P.beta_table[P.k0 + 1 + threadIdx.x] : 0.0f;
+  if (threadIdx.x < kMaxFuse) sBeta[threadIdx.x] = (threadIdx.x < A.T) ? A.beta_table[A.k0 + 1 + threadIdx.x] : 0.0f;
   __syncthreads();
-  const bool last = (P.k0 + Ti == D.iters);
-  const long long px = (long long)D.m * D.n;
-  TileJob J;
-  J.b = reinterpret_cast<const float2*>(P.b) + D.offset;
-  J.mask = (D.support_offset >= 0 && P.support) ? P.support + D.support_offset : nullptr;
-  J.st_in = (P.k0 == 0) ? nullptr : reinterpret_cast<const float4*>(P.st_in) + 2 * D.offset;
-  J.st_out = last ? nullptr : reinterpret_cast<float4*>(P.st_out) + 2 * D.offset;
-  J.x = last ? reinterpret_cast<float2*>(P.x) + D.offset : nullptr;
-  J.m = D.m;
-  J.n = D.n;
-  J.tx = bt.tx;
-  J.ty = bt.ty;
-  J.lam = D.lam;
-  J.c = D.c;
-  J.R = D.R;
-  J.T = Ti;
-  const bool has_mask = J.mask != nullptr;
-  switch (D.kind * 2 + (has_mask ? 1 : 0)) {
-    case 0: fgp_tile<K1I, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
-    case 1: fgp_tile<K1I, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
-    case 2: fgp_tile<K1A, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
-    case 3: fgp_tile<K1A, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
-    case 4: fgp_tile<K2I, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
-    case 5: fgp_tile<K2I, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
-    case 6: fgp_tile<K2A, CONSTR, false, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
-    default: fgp_tile<K2A, CONSTR, true, RH>(J, P.halo, sBeta, sA1, sA2, sY); break;
+  constexpr int kXcd = 8;
+  const int G = gridDim.x;
+  const int xcd = blockIdx.x % kXcd, bi = blockIdx.x / kXcd;
+  const int gx = G / kXcd + (xcd < G % kXcd ? 1 : 0);
+  const int lo = (int)((long long)A.ntiles * xcd / kXcd);
+  const int hi = (int)((long long)A.ntiles * (xcd + 1) / kXcd);
+  for (int t = lo + bi; t < hi; t += gx) {
+    const BatchTile bt = A.tiles[t];
+    const BatchImage D = A.images[bt.image];
+    const int Ti = min(A.T, D.iters - A.k0);
+    const bool last = (A.k0 + Ti == D.iters);
+    const int H = max(1, Ti + (last ? 1 : 0));
+    TileJob J;
+    J.b = reinterpret_cast<const float2*>(A.b) + D.offset;
+    J.mask = (D.support_offset >= 0 && A.support) ? A.support + D.support_offset : nullptr;
+    J.st_in = (A.k0 == 0) ? nullptr : reinterpret_cast<const float4*>(A.st_in) + 2 * D.offset;
+    J.st_out = last ? nullptr : reinterpret_cast<float4*>(A.st_out) + 2 * D.offset;
+    J.x = last ? reinterpret_cast<float2*>(A.x) + D.offset : nullptr;
+    J.m = D.m;
+    J.n = D.n;
+    J.tx = bt.tx;
+    J.ty = bt.ty;
+    J.lam = D.lam;
+    J.c = D.c;
+    J.R = D.R;
+    J.T = Ti;
+    const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (NW * P - 2 * H) - H;
+    const bool interior = c0 >= 1 && c0 + kRW <= J.n - 1 && r0 >= 1 && r0 + NW * P <= J.m - 1;
+    const int sel = (D.kind * 2 + (J.mask ? 1 : 0)) * 2 + (interior ? 0 : 1);
+    switch (sel) {
+#define CTV_B(KI, MK, BO, S)                                                             \
+  case S:                                                                                \
+    fgp_tile_col<KI, CONSTR, MK, NW, P, BO>(J, H, sBeta, sBot, sTop);                    \
+    break;
+      CTV_B(K1I, false, false, 0) CTV_B(K1I, false, true, 1) CTV_B(K1I, true, false, 2) CTV_B(K1I, true, true, 3)
+      CTV_B(K1A, false, false, 4) CTV_B(K1A, false, true, 5) CTV_B(K1A, true, false, 6) CTV_B(K1A, true, true, 7)
+      CTV_B(K2I, false, false, 8) CTV_B(K2I, false, true, 9) CTV_B(K2I, true, false, 10) CTV_B(K2I, true, true, 11)
+      CTV_B(K2A, false, false, 12) CTV_B(K2A, false, true, 13) CTV_B(K2A, true, false, 14)
+      default: fgp_tile_col<K2A, CONSTR, true, NW, P, true>(J, H, sBeta, sBot, sTop); break;
+#undef CTV_B
+    }
+    __syncthreads();  // the next tile reuses the LDS rows
   }
 }
 
@@ -578,21 +591,16 @@ hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const T
   }
 }
 
-const void* fgp_batched_kernel_ptr(int constr, int rh) {
-  if (constr == C_MOD) {
-    if (rh == 32) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, 32>);
-    if (rh == 64) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, 64>);
-    return reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, 16>);
-  }
-  if (rh == 32) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, 32>);
-  if (rh == 64) return reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, 64>);
-  return reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, 16>);
-}
-
-hipError_t launch_fgp_batched(const FgpBatchedArgs& a, int constr, int rh, int nblocks,
-                              hipStream_t s) {
-  void* args[] = {const_cast<FgpBatchedArgs*>(&a)};
-  return hipLaunchKernel(fgp_batched_kernel_ptr(constr, rh), dim3(nblocks), dim3(kThreads), args, 0, s);
+const void* fgp_batched_kernel_ptr(int constr, const TileShape& ts) {
+#define CTV_BK(NW_, P_)                                                                      \
+  if (ts.waves == NW_ && ts.rows_per_thread == P_)                                           \
+    return constr == C_MOD ? reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, NW_, P_>) \
+                           : reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, NW_, P_>);
+  CTV_BK(8, 8)
+  CTV_BK(8, 4)
+  CTV_BK(16, 4)
+#undef CTV_BK
+  return nullptr;
 }
 
 hipError_t launch_project_c(const float* b, const uint8_t* mask, float* x, long long px,

@@ -5,10 +5,6 @@
 using namespace ctv;
 
 extern "C" {
-ctv_status ctv_batched_plan_create(const ctv_image_desc*, int32_t, const ctv_params*, ctv_batched_plan**) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
-ctv_status ctv_batched_workspace_size(const ctv_batched_plan*, size_t*) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
-ctv_status ctv_denoise_batched(ctv_batched_plan*, const float*, const uint8_t*, float*, void*, size_t, ctv_stream_t) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
-ctv_status ctv_batched_plan_destroy(ctv_batched_plan*) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
 ctv_status ctv_backward_workspace_size(const ctv_params*, int32_t, int32_t, int32_t, int32_t, size_t*) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
 ctv_status ctv_denoise_backward(const ctv_params*, int32_t, int32_t, int32_t, const float*, const float*, const uint8_t*, int32_t, const float*, const float*, float*, float*, void*, size_t, ctv_stream_t) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
 ctv_status pr_workspace_size(const pr_params*, int32_t, int32_t, size_t*) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
