@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=12)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary measurements (batched ragged workload, ...)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 1 GiB device-to-device copies (byte-counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -68,6 +70,49 @@ def cpu_baseline(c, sample_iters):
             "sample": f"{len(c['kinds'])} kinds x {sample_iters} FGP iterations on the full "
                       f"{b.shape[0]}x{b.shape[1]} masked image ({dt:.1f} s, numpy float64, single-threaded "
                       f"elementwise; OMP_NUM_THREADS={threads})"}
+
+
+def timed(fn, reps, torch, stream):
+    """Average milliseconds of fn() over reps, bracketed by HIP events."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(ctv, synth, torch, dev, reps=3):
+    """Ragged batch: 256 images with sides ~ U{128..1024}, per-image lambda and
+    kind, 150 iterations, as one HIP-graph launch vs 256 plain calls."""
+    imgs = synth.config3(0)
+    descs = [dict(m=d["b"].shape[0], n=d["b"].shape[1], lam=d["lam"], kind=d["kind"], alpha=0.5,
+                  iters=d["iters"]) for d in imgs]
+    plan = ctv.BatchedPlan(descs)
+    bp = plan.pack([d["b"] for d in imgs], device=dev)
+    xp = torch.empty_like(bp)
+    stream = torch.cuda.current_stream(dev)
+    ms_graph = timed(lambda: plan.run(bp, out=xp), reps, torch, stream)
+    bs = [torch.as_tensor(d["b"]).to(dev) for d in imgs]
+    xs = [torch.empty_like(t) for t in bs]
+    ws = torch.empty(max(ctv.workspace_size(d["m"], d["n"], 1, iters=d["iters"])[0] for d in descs),
+                     dtype=torch.uint8, device=dev)
+
+    def plain_all():
+        for d, t, x in zip(imgs, bs, xs):
+            ctv.denoise(t, d["lam"], kind=d["kind"], iters=d["iters"], out=x, workspace=ws)
+
+    ms_plain = timed(plain_all, reps, torch, stream)
+    same = all(torch.equal(a.view(torch.float32), x.view(torch.float32)) for a, x in zip(plan.unpack(xp), xs))
+    px_it = sum(d["b"].size * d["iters"] for d in imgs)
+    plan.close()
+    return {"workload": "256 complex64 images, sides ~ U{128..1024}, lambda log-U[0.01,0.2], kinds 1i/1a, K=150",
+            "px_iters": px_it, "graph_ms": round(ms_graph, 3), "plain_256_calls_ms": round(ms_plain, 3),
+            "speedup": round(ms_plain / ms_graph, 3), "graph_Mpx_it_s": round(px_it / ms_graph / 1e3, 1),
+            "plain_Mpx_it_s": round(px_it / ms_plain / 1e3, 1), "bitwise_equal_to_plain": bool(same)}
 
 
 def main():
@@ -159,6 +204,8 @@ def main():
            "per_kind_ms": {k: round(v / args.steps, 3) for k, v in per_kind_ms.items()},
            "wall_s": round(wall, 3),
            "roofline": roof}
+    if not args.no_extras:
+        out["batched"] = bench_batched(ctv, synth, torch, dev)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -139,6 +139,7 @@ class CTVDenoise(torch.autograd.Function):
         ctx.save_for_backward(b, saved)
         ctx.lam = lam_vals.cpu().reshape(-1).tolist() if isinstance(lam_vals, torch.Tensor) else lam_vals
         ctx.lam_shape = lam.shape if isinstance(lam, torch.Tensor) else None
+        ctx.lam_meta = (lam.device, lam.dtype) if isinstance(lam, torch.Tensor) else None
         ctx.cfg = (kind, alpha, constraint, support, iters, fuse, ckpt_every)
         return x
 
@@ -152,6 +153,7 @@ class CTVDenoise(torch.autograd.Function):
         if ctx.lam_shape is not None:
             glam = gl.sum().reshape(ctx.lam_shape) if len(ctx.lam_shape) == 0 or ctx.lam_shape.numel() == 1 \
                 else gl.reshape(ctx.lam_shape)
+            glam = glam.to(device=ctx.lam_meta[0], dtype=ctx.lam_meta[1])
         return gb, glam, None, None, None, None, None, None, None
 
 

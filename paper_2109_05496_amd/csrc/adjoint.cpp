@@ -1,0 +1,166 @@
+// Host side of ctv_denoise_backward: segment-wise recomputation from the
+// forward checkpoints (single-iteration launches that keep every r_k), the
+// Eq. (18) output adjoint, one reverse-step launch per iteration, and the
+// deterministic lambda-gradient reduction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctv.h"
+#include "ctv_adjoint.hpp"
+#include "ctv_host.hpp"
+#include "ctv_kernels.hpp"
+
+using namespace ctv;
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int adj_tiles_x(int n) { return (n + (64 - 2 * adj_halo()) - 1) / (64 - 2 * adj_halo()); }
+int adj_tiles_y(int m) { return (m + (adj_tile_rows() - 2 * adj_halo()) - 1) / (adj_tile_rows() - 2 * adj_halo()); }
+
+struct BwdLayout {
+  size_t seg, adj, lam, total;
+};
+
+BwdLayout layout(int batch, int m, int n, int ckpt) {
+  BwdLayout L;
+  const size_t st = align_up(state_bytes(batch, m, n));
+  L.seg = (size_t)std::max(ckpt, 1) * st;
+  L.adj = 2 * st;
+  L.lam = align_up((size_t)batch * adj_tiles_x(n) * adj_tiles_y(m) * sizeof(double));
+  L.total = L.seg + L.adj + L.lam;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctv_status ctv_backward_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int32_t n, int32_t ckpt_every,
+                                       size_t* ws_bytes) {
+  ctv_status st = validate_params(p);
+  if (st) return st;
+  if (batch < 1 || m < 1 || n < 1) return fail(CTV_ERR_INVALID_ARG, "batch, m and n must be >= 1");
+  if (ckpt_every < 1) return fail(CTV_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+  if (!ws_bytes) return fail(CTV_ERR_INVALID_ARG, "ws_bytes is NULL");
+  *ws_bytes = layout(batch, m, n, std::min(ckpt_every, std::max(p->iters, 1))).total;
+  return CTV_OK;
+}
+
+ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, int32_t n, const float* b,
+                                const float* lambda_host, const uint8_t* support, int32_t ckpt_every,
+                                const float* saved, const float* grad_x, float* grad_b, float* grad_lambda,
+                                void* ws, size_t ws_bytes, ctv_stream_t stream) {
+  ctv_status st = validate_params(p);
+  if (st) return st;
+  if (batch < 1 || m < 1 || n < 1) return fail(CTV_ERR_INVALID_ARG, "batch, m and n must be >= 1");
+  if (!b || !lambda_host || !grad_x || !grad_b || !grad_lambda)
+    return fail(CTV_ERR_INVALID_ARG, "b, lambda_host, grad_x, grad_b and grad_lambda must be non-NULL");
+  if (grad_b == b || grad_b == grad_x) return fail(CTV_ERR_INVALID_ARG, "grad_b must not alias b or grad_x");
+  for (int i = 0; i < batch; ++i) {
+    st = validate_lambda(lambda_host[i]);
+    if (st) return st;
+  }
+  if (ckpt_every < 1) return fail(CTV_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+  const int K = p->iters;
+  const int c = std::min(ckpt_every, std::max(K, 1));
+  const int nseg = K > 0 ? (K + c - 1) / c : 0;
+  if (nseg > 1 && !saved) return fail(CTV_ERR_INVALID_ARG, "saved is NULL but the forward stored checkpoints");
+  if (!ws) return fail(CTV_ERR_INVALID_ARG, "ws is NULL");
+  const BwdLayout L = layout(batch, m, n, c);
+  if (ws_bytes < L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long px = (long long)m * n;
+  const size_t st_full = state_bytes(batch, m, n);
+  const size_t st_stride = align_up(st_full);
+  char* wsb = static_cast<char*>(ws);
+  float* seg = reinterpret_cast<float*>(wsb);
+  float* adjX = reinterpret_cast<float*>(wsb + L.seg);
+  float* adjY = reinterpret_cast<float*>(wsb + L.seg + st_stride);
+  double* lam_acc = reinterpret_cast<double*>(wsb + L.seg + L.adj);
+
+  // x = P_C(b) for every image when K = 0; lambda = 0 images go through the
+  // general path (step 0 keeps q = 0) with a zero lambda gradient.
+  if (K == 0) {
+    hipError_t e = launch_pc_vjp(b, support, grad_x, grad_b, px, batch, p->constraint, s);
+    if (e == hipSuccess) e = launch_zero_f32(grad_lambda, batch, s);
+    if (e != hipSuccess) return hip_fail(e, "backward (K = 0)");
+    return CTV_OK;
+  }
+
+  Tiling tl;
+  ctv_params tp = *p;
+  tp.fuse = 1;
+  st = choose_tiling(&tp, m, n, batch, &tl);
+  if (st) return st;
+  tl.T = 1;
+  std::vector<float> beta;
+  momentum_table(K + 1, beta);
+  const int tiles_x = adj_tiles_x(n), tiles_per_img = tiles_x * adj_tiles_y(m);
+
+  for (int c0 = 0; c0 < batch; c0 += kPlainChunk) {
+    const int cb = std::min(kPlainChunk, batch - c0);
+    const long long img_px = px * c0;
+    const long long st_off = 2 * px * c0 * 4;
+    AdjStepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.b = b + 2 * img_px;
+    a.mask = support;
+    a.grad_b = grad_b + 2 * img_px;
+    a.grad_x = grad_x + 2 * img_px;
+    a.lam_acc = lam_acc + (size_t)c0 * tiles_per_img;
+    a.m = m;
+    a.n = n;
+    a.tiles_x = tiles_x;
+    a.tiles_per_img = tiles_per_img;
+    a.R = make_radii(p->tv_kind, p->alpha);
+    for (int i = 0; i < cb; ++i) {
+      const double lam = lambda_host[c0 + i];
+      a.lam[i] = (float)lam;
+      a.c[i] = step_of((float)lam);
+      a.cc[i] = lam > 0.0 ? (float)(1.0 / (8.0 * lam * lam)) : 0.0f;
+    }
+    float* cur = adjX + st_off;
+    float* nxt = adjY + st_off;
+    auto slot = [&](int j) { return seg + (size_t)j * (st_stride / 4) + st_off; };
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+      const int ks = sgi * c, ke = std::min(ks + c, K);
+      const float* ck = (sgi == 0) ? nullptr : saved + (size_t)(sgi - 1) * (st_full / 4) + st_off;
+      // recompute: state after iteration k into slot[k - ks - 1]
+      const int kstop = (sgi == nseg - 1) ? ke : ke - 1;
+      const float* prev = ck;
+      for (int k = ks; k < kstop; ++k) {
+        st = fgp_launch(p, tl, cb, m, n, a.b, support, lambda_host + c0, beta, k, 1, prev, slot(k - ks), nullptr, s);
+        if (st) return st;
+        prev = slot(k - ks);
+      }
+      if (sgi == nseg - 1) {
+        a.r = slot(ke - ks - 1);  // q_K in plane 0
+        a.adj_in = nullptr;
+        a.adj_out = cur;
+        hipError_t e = launch_adj_output(a, p->constraint, cb, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint output step");
+      }
+      for (int k = ke; k >= ks + 1; --k) {
+        a.r = (k == ks + 1) ? ck : slot(k - ks - 2);
+        a.adj_in = cur;
+        a.adj_out = (k == 1) ? nullptr : nxt;
+        a.beta = (k >= 2) ? beta[(size_t)(k - 1)] : 0.0f;
+        hipError_t e = launch_adj_step(a, p->tv_kind, p->constraint, cb, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint step");
+        std::swap(cur, nxt);
+      }
+    }
+    hipError_t e = launch_lam_final(a.lam_acc, tiles_per_img, cb, grad_lambda + c0, s);
+    if (e != hipSuccess) return hip_fail(e, "lambda gradient reduction");
+  }
+  return CTV_OK;
+}
+
+}  // extern "C"

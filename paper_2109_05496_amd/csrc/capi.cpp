@@ -124,6 +124,34 @@ size_t denoise_ws_bytes(int batch, int m, int n) {
   return 2 * st + gap;
 }
 
+ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int n, const float* b,
+                      const uint8_t* support, const float* lam, const std::vector<float>& beta, int k, int Tl,
+                      const float* src, float* dst, float* x, hipStream_t s) {
+  FgpPlainArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.b = b;
+  a.mask = support;
+  a.m = m;
+  a.n = n;
+  a.R = make_radii(p->tv_kind, p->alpha);
+  for (int i = 0; i < cb; ++i) {
+    a.lam[i] = lam[i];
+    a.c[i] = step_of(lam[i]);
+  }
+  a.st_in = src;
+  a.st_out = dst;
+  a.x = x;
+  a.T = Tl;
+  a.halo = std::max(1, Tl + (x ? 1 : 0));
+  for (int i = 0; i < kMaxFuse; ++i) a.beta[i] = (i < Tl) ? beta[(size_t)(k + 1 + i)] : 0.0f;
+  const int rows = tl.shape.rows();
+  a.tiles_x = (n + (64 - 2 * a.halo) - 1) / (64 - 2 * a.halo);
+  a.tiles_y = (m + (rows - 2 * a.halo) - 1) / (rows - 2 * a.halo);
+  hipError_t e = launch_fgp_plain(a, p->tv_kind, p->constraint, tl.shape, cb, s);
+  if (e != hipSuccess) return hip_fail(e, "fgp launch");
+  return CTV_OK;
+}
+
 }  // namespace ctv
 
 using namespace ctv;
@@ -207,17 +235,6 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
     const int cb = std::min(kPlainChunk, batch - c0);
     const long long img_px = px * c0;            // pixel offset of the chunk
     const long long st_off = 2 * px * c0 * 4;    // float offset of the chunk in a state buffer
-    FgpPlainArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.b = b + 2 * img_px;
-    a.mask = support;
-    a.m = m;
-    a.n = n;
-    a.R = R;
-    for (int i = 0; i < cb; ++i) {
-      a.lam[i] = lambda_host[c0 + i];
-      a.c[i] = step_of(lambda_host[c0 + i]);
-    }
     const float* src = state_in ? state_in + st_off : nullptr;
     int k = k0;
     const int kend = k0 + p->iters;
@@ -233,18 +250,9 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
         dst = saved + (size_t)((k + Tl) / ckpt_every - 1) * (st_full / 4) + st_off;
       else
         dst = other;
-      a.st_in = src;
-      a.st_out = dst;
-      a.x = last ? x + 2 * img_px : nullptr;
-      a.T = Tl;
-      a.halo = Tl + (last ? 1 : 0);
-      a.halo = std::max(a.halo, 1);
-      for (int i = 0; i < kMaxFuse; ++i) a.beta[i] = (i < Tl) ? beta[(size_t)(k + 1 + i)] : 0.0f;
-      a.tiles_x = (int)((n + (64 - 2 * a.halo) - 1) / (64 - 2 * a.halo));
-      const int rows = tl.shape.rows();
-      a.tiles_y = (int)((m + (rows - 2 * a.halo) - 1) / (rows - 2 * a.halo));
-      hipError_t e = launch_fgp_plain(a, p->tv_kind, p->constraint, tl.shape, cb, s);
-      if (e != hipSuccess) return hip_fail(e, "fgp launch");
+      st = fgp_launch(p, tl, cb, m, n, b + 2 * img_px, support, lambda_host + c0, beta, k, Tl, src, dst,
+                      last ? x + 2 * img_px : nullptr, s);
+      if (st) return st;
       src = dst;
       k += Tl;
     } while (k < kend);

@@ -27,5 +27,11 @@ ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* o
 size_t state_bytes(long long batch, long long m, long long n);
 int gap_blocks_per_image(long long px);
 size_t denoise_ws_bytes(int batch, int m, int n);
+// One launch of the plain fused kernel: iterations k+1 .. k+Tl on a chunk of
+// cb <= 32 images (per-image lambdas lam[0..cb)), from state src (nullptr =
+// cold start) into dst (nullptr = not stored); x != nullptr adds Eq. (18).
+ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int n, const float* b,
+                      const uint8_t* support, const float* lam, const std::vector<float>& beta, int k, int Tl,
+                      const float* src, float* dst, float* x, hipStream_t s);
 
 }  // namespace ctv

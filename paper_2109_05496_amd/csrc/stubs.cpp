@@ -5,8 +5,6 @@
 using namespace ctv;
 
 extern "C" {
-ctv_status ctv_backward_workspace_size(const ctv_params*, int32_t, int32_t, int32_t, int32_t, size_t*) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
-ctv_status ctv_denoise_backward(const ctv_params*, int32_t, int32_t, int32_t, const float*, const float*, const uint8_t*, int32_t, const float*, const float*, float*, float*, void*, size_t, ctv_stream_t) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
 ctv_status pr_workspace_size(const pr_params*, int32_t, int32_t, size_t*) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
 ctv_status pr_prox_grad(const pr_params*, int32_t, int32_t, const float*, float*, float*, void*, size_t, ctv_stream_t) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
 ctv_status ctv_fft2(int32_t, int32_t, int32_t, const float*, float*, int32_t, ctv_stream_t) { return fail(CTV_ERR_UNSUPPORTED, "not built"); }
