@@ -298,5 +298,8 @@ def fft2(x, inverse=False):
     xx = x.unsqueeze(0) if squeeze else x
     B, m, n = xx.shape
     out = torch.empty_like(xx)
-    call("ctv_fft2", B, m, n, _ptr(xx), _ptr(out), int(bool(inverse)), _stream(x.device))
+    wsb = ctypes.c_size_t()
+    call("ctv_fft2_workspace_size", m, n, ctypes.byref(wsb))
+    ws = torch.empty(max(wsb.value, 1), dtype=torch.uint8, device=x.device)
+    call("ctv_fft2", B, m, n, _ptr(xx), _ptr(out), int(bool(inverse)), _ptr(ws), ws.numel(), _stream(x.device))
     return out[0] if squeeze else out

@@ -1,0 +1,351 @@
+// Host side of the phase-retrieval path: FISTA (Algorithm 1) on the amplitude
+// data term of Eq. (24) summed over the measurement distances, with the
+// constrained-TV FGP denoiser as the proximity operator (Eq. 15, lambda =
+// tau * gamma), plus the stage entry points and the standalone 2-D FFT.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctv.h"
+#include "ctv_host.hpp"
+#include "ctv_pr.hpp"
+
+using namespace ctv;
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct PrLayout {
+  size_t tw_n, tw_m, H, sy, syc, xh, t1, acc, v, xcur, xprev, z, fgp, part, total;
+};
+
+PrLayout pr_layout(int D, int m, int n) {
+  PrLayout L;
+  const size_t px = (size_t)m * n;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  L.tw_n = take((size_t)n * 8);
+  L.tw_m = take((size_t)m * 8);
+  L.H = take((size_t)D * px * 8);
+  L.sy = take((size_t)D * px * 4);
+  L.syc = take(px * 8);
+  L.xh = take(px * 8);
+  L.t1 = take(px * 8);
+  L.acc = take(px * 8);
+  L.v = take(px * 8);
+  L.xcur = take(px * 8);
+  L.xprev = take(px * 8);
+  L.z = take(px * 8);
+  L.fgp = take(denoise_ws_bytes(1, m, n));
+  L.part = take((size_t)D * fft_col_blocks(m, n) * 8);
+  L.total = o;
+  return L;
+}
+
+ctv_status validate_pr(const pr_params* p, int m, int n, bool need_inner) {
+  if (!p) return fail(CTV_ERR_INVALID_ARG, "pr_params is NULL");
+  if (p->struct_size != sizeof(pr_params)) return fail(CTV_ERR_INVALID_ARG, "pr_params.struct_size mismatch");
+  if (p->num_meas < 1 || p->num_meas > 64) return fail(CTV_ERR_INVALID_ARG, "num_meas must lie in [1, 64]");
+  if (!p->distances_host) return fail(CTV_ERR_INVALID_ARG, "distances_host is NULL");
+  for (int d = 0; d < p->num_meas; ++d)
+    if (!std::isfinite(p->distances_host[d])) return fail(CTV_ERR_INVALID_ARG, "non-finite distance");
+  if (!(p->wavelength > 0.0) || !std::isfinite(p->wavelength)) return fail(CTV_ERR_INVALID_ARG, "wavelength must be > 0");
+  if (!(p->pixel > 0.0) || !std::isfinite(p->pixel)) return fail(CTV_ERR_INVALID_ARG, "pixel must be > 0");
+  if (!fft_size_ok(m) || !fft_size_ok(n)) return fail(CTV_ERR_UNSUPPORTED, "m and n must be powers of two in [2, 4096]");
+  if (need_inner) {
+    if (!(p->tau >= 0.0f) || !std::isfinite(p->tau)) return fail(CTV_ERR_INVALID_ARG, "tau must be >= 0");
+    if (!(p->gamma >= 0.0f) || !std::isfinite(p->gamma)) return fail(CTV_ERR_INVALID_ARG, "gamma must be >= 0");
+    if (p->outer_iters < 0) return fail(CTV_ERR_INVALID_ARG, "outer_iters must be >= 0");
+    ctv_status st = validate_params(&p->inner);
+    if (st) return st;
+  }
+  return CTV_OK;
+}
+
+struct Ctx {
+  int m, n, D;
+  long long px;
+  char* ws;
+  PrLayout L;
+  hipStream_t s;
+  float2* at(size_t off) const { return reinterpret_cast<float2*>(ws + off); }
+  float* atf(size_t off) const { return reinterpret_cast<float*>(ws + off); }
+  const float2* H(int d) const { return at(L.H) + (size_t)d * px; }
+  const float* sy(int d) const { return atf(L.sy) + (size_t)d * px; }
+};
+
+FftArgs base_args(const Ctx& c) {
+  FftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.m = c.m;
+  a.n = c.n;
+  a.img_stride = c.px;
+  a.scale = 1.0f;
+  return a;
+}
+
+#define CTV_TRY(expr, what)                   \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// out = FFT2(in) (forward) with the column pass finishing as `post`.
+ctv_status fft2_into(const Ctx& c, const float2* in, float2* tmp, int dir, int post, FftArgs tail) {
+  FftArgs r = base_args(c);
+  r.in = in;
+  r.out = tmp;
+  r.tw = c.at(c.L.tw_n);
+  CTV_TRY(launch_fft_rows(r, dir, kPreNone, 1, c.s), "fft rows");
+  tail.in = tmp;
+  tail.tw = c.at(c.L.tw_m);
+  CTV_TRY(launch_fft_cols(tail, dir, post, 1, c.s), "fft cols");
+  return CTV_OK;
+}
+
+// Tables shared by every phase-retrieval entry point: twiddles, H_d, sqrt(y_d).
+ctv_status build_tables(const Ctx& c, const pr_params* p, const float* y) {
+  CTV_TRY(launch_twiddles(c.at(c.L.tw_n), c.n, c.s), "twiddles");
+  CTV_TRY(launch_twiddles(c.at(c.L.tw_m), c.m, c.s), "twiddles");
+  for (int d = 0; d < c.D; ++d)
+    CTV_TRY(launch_transfer(c.at(c.L.H) + (size_t)d * c.px, c.m, c.n, p->distances_host[d], p->wavelength,
+                            p->pixel, c.s), "transfer function");
+  if (y) CTV_TRY(launch_sqrt_y(y, c.atf(c.L.sy), nullptr, (long long)c.D * c.px, c.s), "sqrt(y)");
+  return CTV_OK;
+}
+
+// grad F at z (Eq. 27 summed over d). post_step: out = z - gamma grad; else out = grad.
+ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, float gamma, float* loss) {
+  const float inv = 1.0f / (float)((double)c.m * c.n);
+  float2* xh = c.at(c.L.xh);
+  float2* t1 = c.at(c.L.t1);
+  float2* acc = c.at(c.L.acc);
+  double* part = reinterpret_cast<double*>(c.ws + c.L.part);
+  const int cb = fft_col_blocks(c.m, c.n);
+  {  // X = FFT2(z)
+    FftArgs t = base_args(c);
+    t.out = xh;
+    ctv_status st = fft2_into(c, z, t1, -1, kPostStore, t);
+    if (st) return st;
+  }
+  for (int d = 0; d < c.D; ++d) {
+    // A_d z = IFFT2(H_d X), then the residual bracket of Eq. (27)
+    FftArgs r = base_args(c);
+    r.in = xh;
+    r.out = t1;
+    r.tw = c.at(c.L.tw_n);
+    r.H = c.H(d);
+    CTV_TRY(launch_fft_rows(r, 1, kPreMulH, 1, c.s), "fft rows");
+    FftArgs q = base_args(c);
+    q.in = t1;
+    q.out = t1;
+    q.tw = c.at(c.L.tw_m);
+    q.scale = inv;
+    q.sy = c.sy(d);
+    q.partial = part + (size_t)d * cb;
+    CTV_TRY(launch_fft_cols(q, 1, kPostResidual, 1, c.s), "fft cols (residual)");
+    // acc (+)= conj(H_d) FFT2(residual)
+    FftArgs t = base_args(c);
+    t.out = t1;
+    t.H = c.H(d);
+    t.acc = acc;
+    t.accumulate = d > 0;
+    ctv_status st = fft2_into(c, t1, t1, -1, kPostAccumulate, t);
+    if (st) return st;
+  }
+  FftArgs t = base_args(c);
+  t.out = out;
+  t.scale = inv;
+  t.z = z;
+  t.gamma = gamma;
+  ctv_status st = fft2_into(c, acc, t1, 1, post_step ? kPostStep : kPostStore, t);
+  if (st) return st;
+  if (loss) CTV_TRY(launch_loss_final(part, c.D * cb, loss, c.s), "loss");
+  return CTV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctv_status ctv_fft2_workspace_size(int32_t m, int32_t n, size_t* ws_bytes) {
+  if (!fft_size_ok(m) || !fft_size_ok(n)) return fail(CTV_ERR_UNSUPPORTED, "m and n must be powers of two in [2, 4096]");
+  if (!ws_bytes) return fail(CTV_ERR_INVALID_ARG, "ws_bytes is NULL");
+  *ws_bytes = align_up((size_t)n * 8) + align_up((size_t)m * 8);
+  return CTV_OK;
+}
+
+ctv_status ctv_fft2(int32_t batch, int32_t m, int32_t n, const float* in, float* out, int32_t inverse, void* ws,
+                    size_t ws_bytes, ctv_stream_t stream) {
+  if (batch < 1) return fail(CTV_ERR_INVALID_ARG, "batch must be >= 1");
+  if (!fft_size_ok(m) || !fft_size_ok(n)) return fail(CTV_ERR_UNSUPPORTED, "m and n must be powers of two in [2, 4096]");
+  if (!in || !out || !ws) return fail(CTV_ERR_INVALID_ARG, "in, out and ws must be non-NULL");
+  const size_t need = align_up((size_t)n * 8) + align_up((size_t)m * 8);
+  if (ws_bytes < need) return fail(CTV_ERR_WORKSPACE, "workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  float2* twn = static_cast<float2*>(ws);
+  float2* twm = reinterpret_cast<float2*>(static_cast<char*>(ws) + align_up((size_t)n * 8));
+  CTV_TRY(launch_twiddles(twn, n, s), "twiddles");
+  CTV_TRY(launch_twiddles(twm, m, s), "twiddles");
+  const int dir = inverse ? 1 : -1;
+  FftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.m = m;
+  a.n = n;
+  a.img_stride = (long long)m * n;
+  a.in = reinterpret_cast<const float2*>(in);
+  a.out = reinterpret_cast<float2*>(out);
+  a.tw = twn;
+  a.scale = 1.0f;
+  CTV_TRY(launch_fft_rows(a, dir, kPreNone, batch, s), "fft rows");
+  a.in = reinterpret_cast<const float2*>(out);
+  a.tw = twm;
+  a.scale = inverse ? (float)(1.0 / ((double)m * n)) : 1.0f;
+  CTV_TRY(launch_fft_cols(a, dir, kPostStore, batch, s), "fft cols");
+  return CTV_OK;
+}
+
+ctv_status pr_workspace_size(const pr_params* p, int32_t m, int32_t n, size_t* ws_bytes) {
+  ctv_status st = validate_pr(p, m, n, false);
+  if (st) return st;
+  if (!ws_bytes) return fail(CTV_ERR_INVALID_ARG, "ws_bytes is NULL");
+  *ws_bytes = pr_layout(p->num_meas, m, n).total;
+  return CTV_OK;
+}
+
+ctv_status pr_forward(const pr_params* p, int32_t m, int32_t n, const float* x, float* out, void* ws,
+                      size_t ws_bytes, ctv_stream_t stream) {
+  ctv_status st = validate_pr(p, m, n, false);
+  if (st) return st;
+  if (!x || !out || !ws) return fail(CTV_ERR_INVALID_ARG, "x, out and ws must be non-NULL");
+  Ctx c{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
+        reinterpret_cast<hipStream_t>(stream)};
+  if (ws_bytes < c.L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small");
+  st = build_tables(c, p, nullptr);
+  if (st) return st;
+  FftArgs t = base_args(c);
+  t.out = c.at(c.L.xh);
+  st = fft2_into(c, reinterpret_cast<const float2*>(x), c.at(c.L.t1), -1, kPostStore, t);
+  if (st) return st;
+  const float inv = 1.0f / (float)((double)m * n);
+  for (int d = 0; d < c.D; ++d) {
+    float2* od = reinterpret_cast<float2*>(out) + (size_t)d * c.px;
+    FftArgs r = base_args(c);
+    r.in = c.at(c.L.xh);
+    r.out = od;
+    r.tw = c.at(c.L.tw_n);
+    r.H = c.H(d);
+    CTV_TRY(launch_fft_rows(r, 1, kPreMulH, 1, c.s), "fft rows");
+    FftArgs q = base_args(c);
+    q.in = od;
+    q.out = od;
+    q.tw = c.at(c.L.tw_m);
+    q.scale = inv;
+    CTV_TRY(launch_fft_cols(q, 1, kPostStore, 1, c.s), "fft cols");
+  }
+  return CTV_OK;
+}
+
+ctv_status pr_gradient(const pr_params* p, int32_t m, int32_t n, const float* y, const float* x, float* grad,
+                       float* loss, void* ws, size_t ws_bytes, ctv_stream_t stream) {
+  ctv_status st = validate_pr(p, m, n, false);
+  if (st) return st;
+  if (!y || !x || !grad || !ws) return fail(CTV_ERR_INVALID_ARG, "y, x, grad and ws must be non-NULL");
+  Ctx c{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
+        reinterpret_cast<hipStream_t>(stream)};
+  if (ws_bytes < c.L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small");
+  st = build_tables(c, p, y);
+  if (st) return st;
+  return gradient(c, reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(grad), false, 0.0f, loss);
+}
+
+ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y, float* x, float* loss_trace,
+                        void* ws, size_t ws_bytes, ctv_stream_t stream) {
+  ctv_status st = validate_pr(p, m, n, true);
+  if (st) return st;
+  if (!y || !x || !ws) return fail(CTV_ERR_INVALID_ARG, "y, x and ws must be non-NULL");
+  Ctx c{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
+        reinterpret_cast<hipStream_t>(stream)};
+  if (ws_bytes < c.L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small");
+  st = build_tables(c, p, y);
+  if (st) return st;
+  float2* xcur = c.at(c.L.xcur);
+  float2* xprev = c.at(c.L.xprev);
+  float2* z = c.at(c.L.z);
+  float2* v = c.at(c.L.v);
+  float2* t1 = c.at(c.L.t1);
+  float2* acc = c.at(c.L.acc);
+  float2* syc = c.at(c.L.syc);
+  const float inv = 1.0f / (float)((double)m * n);
+  if (p->init_backprop) {
+    // x0 = (1/D) sum_d A_d^H sqrt(y_d): the directly back-propagated field (Section VI-A)
+    for (int d = 0; d < c.D; ++d) {
+      CTV_TRY(launch_sqrt_y(y + (size_t)d * c.px, c.atf(c.L.sy) + (size_t)d * c.px, syc, c.px, c.s), "sqrt(y)");
+      FftArgs t = base_args(c);
+      t.out = t1;
+      t.H = c.H(d);
+      t.acc = acc;
+      t.accumulate = d > 0;
+      st = fft2_into(c, syc, t1, -1, kPostAccumulate, t);
+      if (st) return st;
+    }
+    FftArgs t = base_args(c);
+    t.out = xcur;
+    t.scale = inv / (float)c.D;
+    st = fft2_into(c, acc, t1, 1, kPostStore, t);
+    if (st) return st;
+  } else {
+    CTV_TRY(launch_copy_c(reinterpret_cast<const float2*>(x), xcur, c.px, c.s), "copy");
+  }
+  CTV_TRY(launch_copy_c(xcur, xprev, c.px, c.s), "copy");
+  CTV_TRY(launch_copy_c(xcur, z, c.px, c.s), "copy");
+  const float gamma = p->gamma > 0.0f ? p->gamma : 1.0f / (float)c.D;
+  const float lam = (float)((double)p->tau * gamma);
+  Tiling tl;
+  st = choose_tiling(&p->inner, m, n, 1, &tl);
+  if (st) return st;
+  const int Kin = p->inner.iters;
+  std::vector<float> beta;
+  momentum_table(Kin + 1, beta);
+  float* fws = reinterpret_cast<float*>(c.ws + c.L.fgp);
+  const size_t st_floats = state_bytes(1, m, n) / 4;
+  float* fA = fws;
+  float* fB = fws + ((st_floats + 63) & ~(size_t)63);
+  double t = 1.0;
+  for (int k = 0; k < p->outer_iters; ++k) {
+    // v = z_k - gamma grad F(z_k)  (Algorithm 1, line 3's argument)
+    st = gradient(c, z, v, true, gamma, loss_trace ? loss_trace + k : nullptr);
+    if (st) return st;
+    // x_k = prox_{gamma R}(v): Algorithm 2 with lambda = tau gamma, cold dual start
+    int kk = 0;
+    const float* src = nullptr;
+    do {
+      const int Tl = std::min(tl.T, Kin - kk);
+      const bool last = (kk + Tl == Kin);
+      float* dst = last ? nullptr : (src == fA ? fB : fA);
+      st = fgp_launch(&p->inner, tl, 1, m, n, reinterpret_cast<const float*>(v), nullptr, &lam, beta, kk, Tl, src,
+                      dst, last ? reinterpret_cast<float*>(xcur) : nullptr, c.s);
+      if (st) return st;
+      src = dst;
+      kk += Tl;
+    } while (kk < Kin);
+    // t_{k+1}, z_{k+1} = x_k + ((t_k - 1)/t_{k+1}) (x_k - x_{k-1})  (lines 4-5)
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const float b = p->accelerate ? (float)((t - 1.0) / tn) : 0.0f;
+    CTV_TRY(launch_fista(xcur, xprev, z, b, c.px, c.s), "fista step");
+    t = tn;
+  }
+  CTV_TRY(launch_copy_c(xcur, reinterpret_cast<float2*>(x), c.px, c.s), "copy");
+  return CTV_OK;
+}
+
+}  // extern "C"
