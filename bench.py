@@ -115,6 +115,59 @@ def bench_batched(ctv, synth, torch, dev, reps=3):
             "plain_Mpx_it_s": round(px_it / ms_plain / 1e3, 1), "bitwise_equal_to_plain": bool(same)}
 
 
+def bench_adjoint(ctv, synth, torch, dev, reps=3):
+    """16 x 512^2, type-1i, lambda 0.05, K = 50 with checkpoints every 10:
+    forward (storing checkpoints) and hand-written backward."""
+    c = synth.config4(0)
+    b = torch.as_tensor(c["b"]).to(dev)
+    B, m, n = b.shape
+    K, ck = c["iters"], c["ckpt_every"]
+    gx = torch.ones_like(b)
+    stream = torch.cuda.current_stream(dev)
+    state = {}
+
+    def fwd():
+        state["x"], state["saved"] = ctv.denoise(b, c["lam"], kind="1i", iters=K, ckpt_every=ck)
+
+    def bwd():
+        ctv.denoise_backward(b, [c["lam"]] * B, gx, state["saved"], kind="1i", iters=K, ckpt_every=ck)
+
+    ms_f = timed(fwd, reps, torch, stream)
+    ms_b = timed(bwd, reps, torch, stream)
+    px_it = B * m * n * K
+    return {"workload": "16 x 512^2 complex64, type-1i, lambda 0.05, K=50, checkpoints every 10",
+            "forward_ms": round(ms_f, 3), "backward_ms": round(ms_b, 3),
+            "forward_Mpx_it_s": round(px_it / ms_f / 1e3, 1), "backward_Mpx_it_s": round(px_it / ms_b / 1e3, 1),
+            "backward_over_forward": round(ms_b / ms_f, 2)}
+
+
+def bench_pr(ctv, synth, torch, dev, reps=2):
+    """1024^2 object, 4 distances (1.0-2.5 mm, 532 nm, 4 um), Poisson 1000
+    photons/pixel; 100 FISTA iterations x 20 FGP iterations (tau 0.01, gamma 1/4).
+    The measurements are simulated with the library's own propagator."""
+    import numpy as np
+    P = synth.PR_DEFAULTS
+    truth = synth.config5_object(seed=0)
+    m = truth.shape[0]
+    fields = ctv.pr_forward(torch.as_tensor(truth.astype(np.complex64)).to(dev), P["distances"],
+                            P["wavelength"], P["pixel"])
+    inten = (fields.abs() ** 2).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    y = torch.as_tensor(np.stack([synth.poisson_measure(I, P["photons"], rng) for I in inten])).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    def run():
+        out["x"] = ctv.phase_retrieval(y, P["distances"], P["wavelength"], P["pixel"], tau=P["tau"],
+                                       gamma=P["gamma"], outer=P["outer"], inner=P["inner"])
+
+    ms = timed(run, reps, torch, stream)
+    fgp_px_it = m * m * P["outer"] * P["inner"]
+    return {"workload": "1024^2, D=4, 100 outer x 20 FGP iterations, type-1i, |x|<=1",
+            "ms": round(ms, 3), "ms_per_outer_iteration": round(ms / P["outer"], 4),
+            "fgp_Mpx_it_s_equiv": round(fgp_px_it / ms / 1e3, 1), "fft2_per_outer_iteration": 2 * len(P["distances"]) + 2}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -206,6 +259,8 @@ def main():
            "roofline": roof}
     if not args.no_extras:
         out["batched"] = bench_batched(ctv, synth, torch, dev)
+        out["adjoint"] = bench_adjoint(ctv, synth, torch, dev)
+        out["phase_retrieval"] = bench_pr(ctv, synth, torch, dev)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
