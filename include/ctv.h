@@ -211,12 +211,13 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
 /* Stage entry points of the phase-retrieval path (same conventions).
  * ctv_fft2: 2-D DFT of a complex64 [batch][m][n] array (m, n powers of two in
  *   [2, 4096]); out = sum x exp(-2 pi i (j j'/m + k k'/n)); inverse: + sign and
- *   1/(m n). out may equal in. ws: ctv_fft2_workspace_size() bytes (twiddles).
+ *   1/(m n). out may equal in. ws: ctv_fft2_workspace_size() bytes (twiddles and
+ *   one transposed copy of the batch).
  * pr_forward: out[d] = A_d x for every distance (out is [D][m][n] complex64).
  * pr_gradient: grad = sum_d A_d^H[(A_d x / |A_d x|)(|A_d x| - sqrt(y_d))] (Eq. 27,
  *   unit phasor where A_d x = 0), and loss (device float, may be NULL) = F(x).
  * Both take the workspace of pr_workspace_size(). */
-ctv_status ctv_fft2_workspace_size(int32_t m, int32_t n, size_t* ws_bytes);
+ctv_status ctv_fft2_workspace_size(int32_t batch, int32_t m, int32_t n, size_t* ws_bytes);
 ctv_status ctv_fft2(int32_t batch, int32_t m, int32_t n, const float* in, float* out, int32_t inverse,
                     void* ws, size_t ws_bytes, ctv_stream_t stream);
 ctv_status pr_forward(const pr_params* p, int32_t m, int32_t n, const float* x, float* out,

@@ -299,7 +299,7 @@ def fft2(x, inverse=False):
     B, m, n = xx.shape
     out = torch.empty_like(xx)
     wsb = ctypes.c_size_t()
-    call("ctv_fft2_workspace_size", m, n, ctypes.byref(wsb))
+    call("ctv_fft2_workspace_size", B, m, n, ctypes.byref(wsb))
     ws = torch.empty(max(wsb.value, 1), dtype=torch.uint8, device=x.device)
     call("ctv_fft2", B, m, n, _ptr(xx), _ptr(out), int(bool(inverse)), _ptr(ws), ws.numel(), _stream(x.device))
     return out[0] if squeeze else out

@@ -2,39 +2,43 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-
 namespace ctv {
 
 enum FftPre { kPreNone = 0, kPreMulH = 1 };
-enum FftPost { kPostStore = 0, kPostResidual = 1, kPostAccumulate = 2, kPostStep = 3 };
+// kPostAccumulateAll: acc (+)= sum over n_acc images of conj(H_img) * transform
+// (the images are looped inside one launch, so there is no race on acc).
+enum FftPost { kPostStore = 0, kPostResidual = 1, kPostAccumulateAll = 2, kPostStep = 3 };
 
+// One line pass: `lines` lines of length N along the contiguous axis of each
+// batch image. Element p of input image img is in[img * in_stride + p], of
+// output image img out[img * img_stride + p].
 struct FftArgs {
   const float2* in;
   float2* out;
-  int m, n;               // array shape; rows pass transforms length n, column pass length m
-  long long img_stride;   // elements between batch images of in/out
-  const float2* tw;       // twiddles exp(-2 pi i k / N), k < N, for this pass's length
-  const float2* H;        // transfer function [m][n] (PRE mul / POST accumulate)
-  long long H_stride;     // per-batch-image stride of H (0 = shared)
-  const float* sy;        // sqrt(y) for the residual
+  long long in_stride;    // elements between batch images of in (0 = one input shared by all)
+  long long img_stride;   // elements between batch images of out
+  long long lines;        // set by the launcher
+  const float2* tw;       // exp(-2 pi i k / N), k < N
+  int pre, post;          // FftPre / FftPost
+  const float2* H;        // PRE multiply / POST accumulate table (same layout as the pass)
+  long long H_stride;     // per-image stride of H (0 = shared)
+  const float* sy;        // sqrt(y) for the residual (same layout as the pass output)
   long long sy_stride;
   float2* acc;            // accumulation target
   const float2* z;        // base point of the gradient step
   float gamma;
-  float scale;            // applied to the column-pass output
-  double* partial;        // residual loss partials, one per column block
-  int lines;              // set by the launcher
+  float scale;            // applied to the pass output
+  double* partial;        // residual loss partials, one per block (and image)
   int accumulate;         // 0: acc = w, 1: acc += w
+  int n_acc;              // images summed by kPostAccumulateAll
 };
 
 bool fft_size_ok(int v);
-int fft_log2(int v);
-int fft_col_blocks(int m, int n);
-hipError_t launch_fft_rows(FftArgs a, int dir, int pre, int batch, hipStream_t s);
-hipError_t launch_fft_cols(FftArgs a, int dir, int post, int batch, hipStream_t s);
+int fft_line_blocks(int N, long long lines);
+hipError_t launch_fft_lines(FftArgs a, int N, long long lines, int dir, int batch, hipStream_t s);
+hipError_t launch_transpose(const float2* in, float2* out, int R, int C, int batch, hipStream_t s);
 hipError_t launch_twiddles(float2* tw, int N, hipStream_t s);
-hipError_t launch_transfer(float2* H, int m, int n, double dist, double wavelength, double pixel, hipStream_t s);
+hipError_t launch_transfer_t(float2* Ht, int m, int n, double dist, double wavelength, double pixel, hipStream_t s);
 hipError_t launch_sqrt_y(const float* y, float* sy, float2* syc, long long total, hipStream_t s);
 hipError_t launch_fista(const float2* x, float2* xprev, float2* z, float beta, long long total, hipStream_t s);
 hipError_t launch_loss_final(const double* partial, int count, float* out, hipStream_t s);

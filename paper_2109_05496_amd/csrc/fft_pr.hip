@@ -2,16 +2,23 @@
 // propagator of Eq. (23) and the elementwise pieces of the amplitude
 // data-fidelity gradient of Eq. (27) and of FISTA (Algorithm 1).
 //
-// FFT: lines of length N (a power of two <= 4096) held in LDS, radix-4
-// Stockham passes (plus one radix-2 pass when log2 N is odd), each pass reading
-// all of its butterfly inputs before a barrier and writing them after, so one
-// LDS buffer suffices. A 2-D transform is a row pass (rows are contiguous) and
-// a column pass (a tile of C columns loaded transposed into padded LDS). The
-// column pass can finish with one of the phase-retrieval steps, and the row
-// pass can start with the multiplication by the transfer function, so the
-// intermediate arrays make no extra trips through HBM.
-// Twiddles and the transfer functions are built on the device in float64
-// (the propagation phase 2 pi d / lambda reaches ~3e4 rad) and stored as float2.
+// FFT of lines of length N = 2^L along rows (the contiguous axis):
+//   * N >= 32: N/16 threads per line. Radix-16 Stockham passes run in
+//     registers (a 16-point DFT per thread per pass), followed by one radix-8,
+//     -4 or -2 pass when L is not a multiple of 4. The first pass reads its
+//     inputs straight from global memory and the last pass writes straight to
+//     global memory, both coalesced; only the passes in between exchange data
+//     through LDS (2 exchanges for N = 1024).
+//   * N <= 16: one thread per line, one DFT in registers.
+// A 2-D transform is a row pass, a tiled transpose and a second row pass, so
+// the spectrum lives transposed ([n][m]); the inverse transform starts from
+// that layout and ends in the natural one, and the transfer functions are
+// built transposed, so each FFT2 / IFFT2 costs two line passes and one
+// transpose. The first pass can multiply by a table on load (H_d), the last can
+// store, form the Eq. (27) residual with float64 loss partials, accumulate
+// conj(H_d) * (.), or take the gradient step z - gamma * (.).
+// Twiddles and transfer functions are built on the device in float64 (the
+// propagation phase 2 pi d / lambda_s reaches ~3e4 rad) and stored as float2.
 #include <hip/hip_runtime.h>
 
 #include "ctv_device.hpp"
@@ -28,131 +35,87 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
-// DIR = -1: forward (exp(-2 pi i ...)); DIR = +1: inverse (unnormalised).
+// multiply by exp(DIR * i * pi / 2) = DIR < 0 ? -i : +i
 template <int DIR>
-__device__ __forceinline__ float2 twiddle(const float2* tw, int idx) {
-  const float2 w = tw[idx];
-  return DIR < 0 ? w : conjf2(w);
+__device__ __forceinline__ float2 rot90(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
 
-// y_k = sum_r a_r exp(DIR 2 pi i r k / 4)
 template <int DIR>
-__device__ __forceinline__ void radix4(float2& a0, float2& a1, float2& a2, float2& a3) {
-  const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
-  const float2 d = csub(a1, a3);
-  // forward: multiply by -i; inverse: by +i
-  const float2 t3 = DIR < 0 ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+__device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+  const float2 t = a0;
+  a0 = cadd(t, a1);
+  a1 = csub(t, a1);
+}
+
+// X_k = sum_r a_r exp(DIR 2 pi i r k / 4)
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = rot90<DIR>(csub(a1, a3));
   a0 = cadd(t0, t2);
   a2 = csub(t0, t2);
   a1 = cadd(t1, t3);
   a3 = csub(t1, t3);
 }
 
-constexpr int kThreads = 256;
-constexpr int kMaxB4 = 8;   // radix-4 butterflies per thread per pass (lines * N <= 8192)
-constexpr int kMaxB2 = 16;  // radix-2 butterflies per thread per pass
-
-// Transform `lines` lines of length N stored at s[l*LS + e].
+// exp(DIR 2 pi i t / 16) for t = 0..15 (constants, float64-rounded)
 template <int DIR>
-__device__ void lds_fft(float2* s, int N, int lines, int LS, const float2* __restrict__ tw) {
-  const int tid = threadIdx.x;
-  int Ns = 1;
-  const int q4 = N >> 2;
-  const int total4 = lines * q4;
-  while (Ns * 4 <= N) {
-    float2 v[kMaxB4][4];
-    int dst[kMaxB4];
+__device__ __forceinline__ float2 w16(int t) {
+  constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+  const float cs[16] = {1.0f, c1, h, s1, 0.0f, -s1, -h, -c1, -1.0f, -c1, -h, -s1, 0.0f, s1, h, c1};
+  const float sn[16] = {0.0f, s1, h, c1, 1.0f, c1, h, s1, 0.0f, -s1, -h, -c1, -1.0f, -c1, -h, -s1};
+  return make_float2(cs[t & 15], DIR < 0 ? -sn[t & 15] : sn[t & 15]);
+}
+
+// In-register DFT of length R in {2, 4, 8, 16}: v[k] <- sum_r v[r] exp(DIR 2 pi i r k / R)
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2 (&v)[16]) {
+  if (R == 2) {
+    dft2<DIR>(v[0], v[1]);
+  } else if (R == 4) {
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
+  } else if (R == 8) {
+    // n = 2 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle W8^(n2 k1), DFT2 over n2
+    float2 y[2][4];
 #pragma unroll
-    for (int c = 0; c < kMaxB4; ++c) {
-      const int t = tid + c * kThreads;
-      dst[c] = -1;
-      if (t < total4) {
-        const int l = t / q4, j = t - l * q4;
-        const float2* L = s + l * LS;
-        const int k = j & (Ns - 1);
-        const int step = (N / (4 * Ns)) * k;
-        float2 a0 = L[j], a1 = L[j + q4], a2 = L[j + 2 * q4], a3 = L[j + 3 * q4];
-        if (k) {
-          a1 = cmul(a1, twiddle<DIR>(tw, step));
-          a2 = cmul(a2, twiddle<DIR>(tw, 2 * step));
-          a3 = cmul(a3, twiddle<DIR>(tw, 3 * step));
-        }
-        radix4<DIR>(a0, a1, a2, a3);
-        v[c][0] = a0;
-        v[c][1] = a1;
-        v[c][2] = a2;
-        v[c][3] = a3;
-        dst[c] = l * LS + ((j - k) << 2) + k;
-      }
+    for (int n2 = 0; n2 < 2; ++n2) {
+      float2 a0 = v[n2], a1 = v[2 + n2], a2 = v[4 + n2], a3 = v[6 + n2];
+      dft4<DIR>(a0, a1, a2, a3);
+      y[n2][0] = a0;
+      y[n2][1] = cmul(a1, w16<DIR>(2 * n2));
+      y[n2][2] = cmul(a2, w16<DIR>(4 * n2));
+      y[n2][3] = cmul(a3, w16<DIR>(6 * n2));
     }
-    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kMaxB4; ++c) {
-      if (dst[c] >= 0) {
-        s[dst[c]] = v[c][0];
-        s[dst[c] + Ns] = v[c][1];
-        s[dst[c] + 2 * Ns] = v[c][2];
-        s[dst[c] + 3 * Ns] = v[c][3];
-      }
+    for (int k1 = 0; k1 < 4; ++k1) {
+      v[k1] = cadd(y[0][k1], y[1][k1]);
+      v[k1 + 4] = csub(y[0][k1], y[1][k1]);
     }
-    __syncthreads();
-    Ns *= 4;
-  }
-  if (Ns < N) {  // one radix-2 pass (log2 N odd)
-    const int q2 = N >> 1;
-    const int total2 = lines * q2;
-    float2 v0[kMaxB2], v1[kMaxB2];
-    int dst[kMaxB2];
+  } else {
+    // n = 4 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle W16^(n2 k1), DFT4 over n2
+    float2 y[4][4];
 #pragma unroll
-    for (int c = 0; c < kMaxB2; ++c) {
-      const int t = tid + c * kThreads;
-      dst[c] = -1;
-      if (t < total2) {
-        const int l = t / q2, j = t - l * q2;
-        const float2* L = s + l * LS;
-        const int k = j & (Ns - 1);
-        float2 a0 = L[j], a1 = L[j + q2];
-        if (k) a1 = cmul(a1, twiddle<DIR>(tw, (N / (2 * Ns)) * k));
-        v0[c] = cadd(a0, a1);
-        v1[c] = csub(a0, a1);
-        dst[c] = l * LS + ((j - k) << 1) + k;
-      }
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
+      dft4<DIR>(a0, a1, a2, a3);
+      y[n2][0] = a0;
+      y[n2][1] = n2 ? cmul(a1, w16<DIR>(n2)) : a1;
+      y[n2][2] = n2 ? cmul(a2, w16<DIR>(2 * n2)) : a2;
+      y[n2][3] = n2 ? cmul(a3, w16<DIR>(3 * n2)) : a3;
     }
-    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kMaxB2; ++c) {
-      if (dst[c] >= 0) {
-        s[dst[c]] = v0[c];
-        s[dst[c] + Ns] = v1[c];
-      }
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 a0 = y[0][k1], a1 = y[1][k1], a2 = y[2][k1], a3 = y[3][k1];
+      dft4<DIR>(a0, a1, a2, a3);
+      v[k1] = a0;
+      v[k1 + 4] = a1;
+      v[k1 + 8] = a2;
+      v[k1 + 12] = a3;
     }
-    __syncthreads();
   }
 }
 
-template <int DIR, int PRE>
-__global__ __launch_bounds__(kThreads) void fft_rows_kernel(FftArgs a) {
-  extern __shared__ float2 s[];
-  const int N = a.n, LS = N + 1;
-  const int img = blockIdx.y;
-  const int row0 = blockIdx.x * a.lines;
-  const float2* in = a.in + (long long)img * a.img_stride;
-  float2* out = a.out + (long long)img * a.img_stride;
-  const float2* H = a.H ? a.H + (long long)img * a.H_stride : nullptr;
-  for (int t = threadIdx.x; t < a.lines * N; t += kThreads) {
-    const int l = t / N, c = t - l * N;
-    const long long p = (long long)(row0 + l) * N + c;
-    float2 v = in[p];
-    if (PRE == kPreMulH) v = cmul(v, H[p]);
-    s[l * LS + c] = v;
-  }
-  __syncthreads();
-  lds_fft<DIR>(s, N, a.lines, LS, a.tw);
-  for (int t = threadIdx.x; t < a.lines * N; t += kThreads) {
-    const int l = t / N, c = t - l * N;
-    out[(long long)(row0 + l) * N + c] = s[l * LS + c];
-  }
-}
+constexpr int kThreads = 256;
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -166,55 +129,247 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-template <int DIR, int POST>
-__global__ __launch_bounds__(kThreads) void fft_cols_kernel(FftArgs a) {
-  extern __shared__ float2 s[];
-  __shared__ double red[kThreads / 64];
-  const int M = a.m, N = a.n, C = a.lines, LS = M + 1;
-  const int img = blockIdx.y;
-  const int c0 = xcd_remap(blockIdx.x, gridDim.x) * C;
+// The last-pass epilogue applied to the element at linear index p of image `img`.
+__device__ __forceinline__ void post_op(const FftArgs& a, int img, long long p, float2 v, double& loss) {
+  v.x *= a.scale;
+  v.y *= a.scale;
   const long long base = (long long)img * a.img_stride;
-  const float2* in = a.in + base;
-  for (int t = threadIdx.x; t < M * C; t += kThreads) {
-    const int i = t / C, cc = t - i * C;
-    s[cc * LS + i] = in[(long long)i * N + c0 + cc];
+  if (a.post == kPostStore) {
+    a.out[base + p] = v;
+  } else if (a.post == kPostResidual) {
+    // (A x / |A x|)(|A x| - sqrt(y)): the bracket of Eq. (27), unit phasor where A x = 0
+    const float am = sqrtf(v.x * v.x + v.y * v.y);
+    const float r = am - a.sy[(long long)img * a.sy_stride + p];
+    float2 ph = make_float2(1.0f, 0.0f);
+    if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
+    a.out[base + p] = make_float2(ph.x * r, ph.y * r);
+    loss += 0.5 * (double)r * (double)r;
+  } else {  // kPostStep
+    const float2 z = a.z[p];
+    a.out[base + p] = make_float2(fmaf(-a.gamma, v.x, z.x), fmaf(-a.gamma, v.y, z.y));
   }
+}
+
+__device__ __forceinline__ float2 pre_op(const FftArgs& a, int img, long long p, float2 v) {
+  return a.pre == kPreMulH ? cmul(v, a.H[(long long)img * a.H_stride + p]) : v;
+}
+
+template <int DIR>
+__device__ __forceinline__ float2 tw_load(const float2* __restrict__ tw, int idx) {
+  const float2 w = tw[idx];
+  return DIR < 0 ? w : conjf2(w);
+}
+
+// One Stockham pass of radix R over an LDS line (Ns = size of the sub-transforms
+// already done); the thread handles butterflies j0, j0 + TPL, ... < N/R.
+// LDS index with one pad element per 16: the strided writes of a pass spread
+// over the banks instead of landing on one.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+
+template <int N, int R, int DIR, int TPL>
+__device__ __forceinline__ void pass_lds(const float2* L, float2 (&v)[16], int j, int Ns,
+                                         const float2* __restrict__ tw) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = L[pidx(j + r * (N / R))];
+  const int k = j & (Ns - 1);
+  if (k) {
+    const int step = (N / (Ns * R)) * k;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw_load<DIR>(tw, r * step));
+  }
+  dft<R, DIR>(v);
+}
+
+// The FFT of one line (image `img`, line `line`) up to the last pass, whose 16
+// outputs per thread are returned in o[] with their positions within the line.
+template <int N, int DIR>
+__device__ __forceinline__ void line_fft(const FftArgs& a, int img, long long line, bool live, float2* sl,
+                                         float2 (&o)[16], int (&pos)[16]) {
+  constexpr int TPL = N / 16;                  // threads per line
+  constexpr int L = (N == 32) ? 5 : (N == 64) ? 6 : (N == 128) ? 7 : (N == 256) ? 8 : (N == 512) ? 9
+                  : (N == 1024) ? 10 : (N == 2048) ? 11 : 12;
+  constexpr int P16 = L / 4;                   // radix-16 passes
+  constexpr int RR = 1 << (L % 4);             // remainder radix (1 = none)
+  constexpr int NPASS = P16 + (RR > 1 ? 1 : 0);  // >= 2 for N >= 32
+  const int lt = threadIdx.x % TPL;
+  const long long rowbase = line * N;
+  const float2* in = a.in + (long long)img * a.in_stride;
+  float2 v[16];
+  // pass 1: radix 16 straight from global memory (Ns = 1, no twiddles)
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = pre_op(a, img, rowbase + lt + r * TPL, in[rowbase + lt + r * TPL]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
+  }
+  dft<16, DIR>(v);
+  int Ns = 16;
+  __syncthreads();  // the previous use of this LDS line (an earlier image) is finished
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sl[pidx(lt * 16 + r)] = v[r];
   __syncthreads();
-  lds_fft<DIR>(s, M, C, LS, a.tw);
-  double loss = 0.0;
-  for (int t = threadIdx.x; t < M * C; t += kThreads) {
-    const int i = t / C, cc = t - i * C;
-    const long long p = (long long)i * N + c0 + cc;
-    float2 v = s[cc * LS + i];
-    v.x *= a.scale;
-    v.y *= a.scale;
-    if (POST == kPostStore) {
-      a.out[base + p] = v;
-    } else if (POST == kPostResidual) {
-      // (A x / |A x|) (|A x| - sqrt(y)), the bracket of Eq. (27); unit phasor at 0
-      const float am = sqrtf(v.x * v.x + v.y * v.y);
-      const float sy = a.sy[(long long)img * a.sy_stride + p];
-      const float r = am - sy;
-      float2 ph = make_float2(1.0f, 0.0f);
-      if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
-      a.out[base + p] = make_float2(ph.x * r, ph.y * r);
-      loss += 0.5 * (double)r * (double)r;
-    } else if (POST == kPostAccumulate) {
-      const float2 w = cmul(conjf2(a.H[(long long)img * a.H_stride + p]), v);
-      if (a.accumulate) {
-        const float2 o = a.acc[p];
-        a.acc[p] = cadd(o, w);
+#pragma unroll
+  for (int p = 1; p < NPASS; ++p) {
+    const bool last = (p == NPASS - 1);
+    if (p < P16) {
+      pass_lds<N, 16, DIR, TPL>(sl, v, lt, Ns, a.tw);
+      const int k = lt & (Ns - 1);
+      const int d = (lt - k) * 16 + k;
+      if (!last) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sl[pidx(d + r * Ns)] = v[r];
+        __syncthreads();
       } else {
-        a.acc[p] = w;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          o[r] = v[r];
+          pos[r] = d + r * Ns;
+        }
       }
-    } else {  // kPostStep: out = z - gamma * v
-      const float2 z = a.z[p];
-      a.out[base + p] = make_float2(fmaf(-a.gamma, v.x, z.x), fmaf(-a.gamma, v.y, z.y));
+      Ns *= 16;
+    } else {
+      // remainder pass of radix RR (always the last): 16/RR butterflies per thread
+      constexpr int B = 16 / RR;
+#pragma unroll
+      for (int bb = 0; bb < B; ++bb) {
+        float2 w[16];
+        const int j = lt + bb * TPL;
+        pass_lds<N, RR, DIR, TPL>(sl, w, j, Ns, a.tw);
+        const int k = j & (Ns - 1);
+        const int d = (j - k) * RR + k;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          o[bb * RR + r] = w[r];
+          pos[bb * RR + r] = d + r * Ns;
+        }
+      }
+      Ns *= RR;
     }
   }
-  if (POST == kPostResidual) {
+}
+
+template <int N, int DIR, bool ACCALL>
+__global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
+  constexpr int TPL = N / 16;
+  constexpr int LPB = kThreads / TPL;          // lines per block
+  constexpr int LS = N + N / 16;               // padded LDS line length
+  __shared__ float2 s[LPB * LS];
+  __shared__ double red[kThreads / 64];
+  const int li = threadIdx.x / TPL;
+  const long long line = (long long)blockIdx.x * LPB + li;
+  const bool live = line < a.lines;
+  float2* sl = s + li * LS;
+  float2 o[16];
+  int pos[16];
+  if (ACCALL) {
+    // acc (+)= sum over the n_acc images of conj(H_img) * FFT(line of image img)
+    float2 sum[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sum[r] = make_float2(0.0f, 0.0f);
+    for (int img = 0; img < a.n_acc; ++img) {
+      line_fft<N, DIR>(a, img, line, live, sl, o, pos);
+      if (live) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float2 h = a.H[(long long)img * a.H_stride + line * N + pos[r]];
+          sum[r] = cadd(sum[r], cmul(conjf2(h), make_float2(o[r].x * a.scale, o[r].y * a.scale)));
+        }
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long p = line * N + pos[r];
+        a.acc[p] = a.accumulate ? cadd(a.acc[p], sum[r]) : sum[r];
+      }
+    }
+    return;
+  }
+  const int img = blockIdx.y;
+  line_fft<N, DIR>(a, img, line, live, sl, o, pos);
+  double loss = 0.0;
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) post_op(a, img, line * N + pos[r], o[r], loss);
+  }
+  if (a.post == kPostResidual) {
     const double tot = block_sum(loss, red);
     if (threadIdx.x == 0) a.partial[(long long)img * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+// N <= 16: one thread per line.
+template <int N, int DIR, bool ACCALL>
+__global__ __launch_bounds__(kThreads) void fft_small_kernel(FftArgs a) {
+  __shared__ double red[kThreads / 64];
+  const long long line = (long long)blockIdx.x * kThreads + threadIdx.x;
+  double loss = 0.0;
+  if (ACCALL) {
+    if (line >= a.lines) return;
+    float2 sum[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sum[r] = make_float2(0.0f, 0.0f);
+    for (int img = 0; img < a.n_acc; ++img) {
+      const float2* in = a.in + (long long)img * a.in_stride;
+      float2 v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int r = 0; r < N; ++r) v[r] = pre_op(a, img, line * N + r, in[line * N + r]);
+      dft<N, DIR>(v);
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        const float2 h = a.H[(long long)img * a.H_stride + line * N + r];
+        sum[r] = cadd(sum[r], cmul(conjf2(h), make_float2(v[r].x * a.scale, v[r].y * a.scale)));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const long long p = line * N + r;
+      a.acc[p] = a.accumulate ? cadd(a.acc[p], sum[r]) : sum[r];
+    }
+    return;
+  }
+  const int img = blockIdx.y;
+  if (line < a.lines) {
+    const float2* in = a.in + (long long)img * a.in_stride;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = pre_op(a, img, line * N + r, in[line * N + r]);
+    dft<N, DIR>(v);
+#pragma unroll
+    for (int r = 0; r < N; ++r) post_op(a, img, line * N + r, v[r], loss);
+  }
+  if (a.post == kPostResidual) {
+    const double tot = block_sum(loss, red);
+    if (threadIdx.x == 0) a.partial[(long long)img * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+// out[c][r] = in[r][c] for an R x C complex array per image, 64 x 64 tiles.
+__global__ __launch_bounds__(kThreads) void transpose_kernel(const float2* __restrict__ in, float2* __restrict__ out,
+                                                              int R, int C, long long stride) {
+  __shared__ float2 t[64][65];
+  const int tilesC = (C + 63) / 64;
+  const int tile = blockIdx.x;
+  const int tr = tile / tilesC, tc = tile - tr * tilesC;
+  const float2* src = in + (long long)blockIdx.y * stride;
+  float2* dst = out + (long long)blockIdx.y * stride;
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = tr * 64 + ly + 4 * i, c = tc * 64 + lx;
+    if (r < R && c < C) t[ly + 4 * i][lx] = src[(long long)r * C + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int c = tc * 64 + ly + 4 * i, r = tr * 64 + lx;
+    if (r < R && c < C) dst[(long long)c * R + r] = t[lx][ly + 4 * i];
   }
 }
 
@@ -226,13 +381,14 @@ __global__ __launch_bounds__(256) void twiddle_kernel(float2* tw, int N) {
   tw[k] = make_float2((float)cs, (float)sn);
 }
 
-// H_d(f_x, f_y) of Eq. (23) on the unshifted FFT frequency grid; zero on the
-// evanescent band. Frequencies as numpy.fft.fftfreq(n, pixel).
-__global__ __launch_bounds__(256) void transfer_kernel(float2* H, int m, int n, double dist, double wavelength,
-                                                       double pixel) {
+// H_d(f_x, f_y) of Eq. (23) on the unshifted FFT frequency grid (numpy's fftfreq
+// order), zero on the evanescent band, stored transposed: H_t[j][i] for row
+// frequency index i (of m) and column frequency index j (of n).
+__global__ __launch_bounds__(256) void transfer_t_kernel(float2* Ht, int m, int n, double dist, double wavelength,
+                                                         double pixel) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= (long long)m * n) return;
-  const int i = (int)(p / n), j = (int)(p - (long long)i * n);
+  const int j = (int)(p / m), i = (int)(p - (long long)j * m);
   const double fy = (double)(i < (m + 1) / 2 ? i : i - m) / ((double)m * pixel);
   const double fx = (double)(j < (n + 1) / 2 ? j : j - n) / ((double)n * pixel);
   const double arg = 1.0 - (wavelength * fx) * (wavelength * fx) - (wavelength * fy) * (wavelength * fy);
@@ -243,7 +399,7 @@ __global__ __launch_bounds__(256) void transfer_kernel(float2* H, int m, int n, 
     sincospi(ph, &sn, &cs);
     h = make_float2((float)cs, (float)sn);
   }
-  H[p] = h;
+  Ht[p] = h;
 }
 
 __global__ __launch_bounds__(256) void sqrt_y_kernel(const float* __restrict__ y, float* __restrict__ sy,
@@ -278,61 +434,55 @@ __global__ __launch_bounds__(256) void copy_c_kernel(const float2* __restrict__ 
   if (p < total) b[p] = a[p];
 }
 
-int ilog2(int v) {
-  int l = 0;
-  while ((1 << l) < v) ++l;
-  return l;
+template <int DIR, bool ACCALL>
+hipError_t launch_line_dir(const FftArgs& a, int N, int batch, hipStream_t s) {
+  const long long lines = a.lines;
+  if (N <= 16) {
+    const dim3 grid((unsigned)((lines + kThreads - 1) / kThreads), (unsigned)batch);
+    switch (N) {
+      case 2: hipLaunchKernelGGL((fft_small_kernel<2, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+      case 4: hipLaunchKernelGGL((fft_small_kernel<4, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+      case 8: hipLaunchKernelGGL((fft_small_kernel<8, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((fft_small_kernel<16, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    }
+    return hipGetLastError();
+  }
+  const int lpb = kThreads / (N / 16);
+  const dim3 grid((unsigned)((lines + lpb - 1) / lpb), (unsigned)batch);
+  switch (N) {
+    case 32: hipLaunchKernelGGL((fft_line_kernel<32, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((fft_line_kernel<64, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((fft_line_kernel<128, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((fft_line_kernel<256, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    case 512: hipLaunchKernelGGL((fft_line_kernel<512, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    case 1024: hipLaunchKernelGGL((fft_line_kernel<1024, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    case 2048: hipLaunchKernelGGL((fft_line_kernel<2048, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((fft_line_kernel<4096, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
 bool fft_size_ok(int v) { return v >= 2 && v <= 4096 && (v & (v - 1)) == 0; }
 
-int fft_row_lines(int m, int n, int batch) {
-  int lines = std::max(1, 8192 / n);
-  while (lines > 1 && (lines > m || (long long)(m / lines) * batch < 512)) lines >>= 1;
-  return lines;
+int fft_line_blocks(int N, long long lines) {
+  if (N <= 16) return (int)((lines + kThreads - 1) / kThreads);
+  const int lpb = kThreads / (N / 16);
+  return (int)((lines + lpb - 1) / lpb);
 }
 
-int fft_col_lines(int m, int n) {
-  int c = std::max(1, std::min(8, 8192 / m));
-  while (c > n) c >>= 1;
-  return c;
+hipError_t launch_fft_lines(FftArgs a, int N, long long lines, int dir, int batch, hipStream_t s) {
+  a.lines = lines;
+  if (a.post == kPostAccumulateAll)  // the images are looped inside the kernel
+    return dir < 0 ? launch_line_dir<-1, true>(a, N, 1, s) : launch_line_dir<1, true>(a, N, 1, s);
+  return dir < 0 ? launch_line_dir<-1, false>(a, N, batch, s) : launch_line_dir<1, false>(a, N, batch, s);
 }
 
-hipError_t launch_fft_rows(FftArgs a, int dir, int pre, int batch, hipStream_t s) {
-  a.lines = fft_row_lines(a.m, a.n, batch);
-  const dim3 grid((unsigned)(a.m / a.lines), (unsigned)batch);
-  const size_t lds = (size_t)a.lines * (a.n + 1) * sizeof(float2);
-  if (dir < 0) {
-    if (pre == kPreMulH) hipLaunchKernelGGL((fft_rows_kernel<-1, kPreMulH>), grid, dim3(kThreads), lds, s, a);
-    else hipLaunchKernelGGL((fft_rows_kernel<-1, kPreNone>), grid, dim3(kThreads), lds, s, a);
-  } else {
-    if (pre == kPreMulH) hipLaunchKernelGGL((fft_rows_kernel<1, kPreMulH>), grid, dim3(kThreads), lds, s, a);
-    else hipLaunchKernelGGL((fft_rows_kernel<1, kPreNone>), grid, dim3(kThreads), lds, s, a);
-  }
-  return hipGetLastError();
-}
-
-int fft_col_blocks(int m, int n) { return n / fft_col_lines(m, n); }
-
-hipError_t launch_fft_cols(FftArgs a, int dir, int post, int batch, hipStream_t s) {
-  a.lines = fft_col_lines(a.m, a.n);
-  const dim3 grid((unsigned)(a.n / a.lines), (unsigned)batch);
-  const size_t lds = (size_t)a.lines * (a.m + 1) * sizeof(float2);
-#define CTV_COLS(D_)                                                                                     \
-  switch (post) {                                                                                        \
-    case kPostStore: hipLaunchKernelGGL((fft_cols_kernel<D_, kPostStore>), grid, dim3(kThreads), lds, s, a); break; \
-    case kPostResidual: hipLaunchKernelGGL((fft_cols_kernel<D_, kPostResidual>), grid, dim3(kThreads), lds, s, a); break; \
-    case kPostAccumulate: hipLaunchKernelGGL((fft_cols_kernel<D_, kPostAccumulate>), grid, dim3(kThreads), lds, s, a); break; \
-    default: hipLaunchKernelGGL((fft_cols_kernel<D_, kPostStep>), grid, dim3(kThreads), lds, s, a); break; \
-  }
-  if (dir < 0) {
-    CTV_COLS(-1)
-  } else {
-    CTV_COLS(1)
-  }
-#undef CTV_COLS
+hipError_t launch_transpose(const float2* in, float2* out, int R, int C, int batch, hipStream_t s) {
+  const int tiles = ((R + 63) / 64) * ((C + 63) / 64);
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)tiles, (unsigned)batch), dim3(kThreads), 0, s, in, out, R, C,
+                     (long long)R * C);
   return hipGetLastError();
 }
 
@@ -341,9 +491,9 @@ hipError_t launch_twiddles(float2* tw, int N, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_transfer(float2* H, int m, int n, double dist, double wavelength, double pixel, hipStream_t s) {
+hipError_t launch_transfer_t(float2* Ht, int m, int n, double dist, double wavelength, double pixel, hipStream_t s) {
   const long long total = (long long)m * n;
-  hipLaunchKernelGGL(transfer_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, H, m, n, dist,
+  hipLaunchKernelGGL(transfer_t_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Ht, m, n, dist,
                      wavelength, pixel);
   return hipGetLastError();
 }
@@ -367,7 +517,5 @@ hipError_t launch_copy_c(const float2* a, float2* b, long long total, hipStream_
   hipLaunchKernelGGL(copy_c_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, b, total);
   return hipGetLastError();
 }
-
-int fft_log2(int v) { return ilog2(v); }
 
 }  // namespace ctv

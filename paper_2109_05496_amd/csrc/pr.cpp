@@ -21,8 +21,10 @@ namespace {
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct PrLayout {
-  size_t tw_n, tw_m, H, sy, syc, xh, t1, acc, v, xcur, xprev, z, fgp, part, total;
+  size_t tw_n, tw_m, H, sy, syc, xh, t1, t2, acc, v, xcur, xprev, z, fgp, part, total;
 };
+
+int residual_blocks(int m, int n) { return fft_line_blocks(n, m); }
 
 PrLayout pr_layout(int D, int m, int n) {
   PrLayout L;
@@ -35,18 +37,19 @@ PrLayout pr_layout(int D, int m, int n) {
   };
   L.tw_n = take((size_t)n * 8);
   L.tw_m = take((size_t)m * 8);
-  L.H = take((size_t)D * px * 8);
+  L.H = take((size_t)D * px * 8);  // transposed transfer functions [D][n][m]
   L.sy = take((size_t)D * px * 4);
-  L.syc = take(px * 8);
+  L.syc = take((size_t)D * px * 8);
   L.xh = take(px * 8);
-  L.t1 = take(px * 8);
+  L.t1 = take((size_t)D * px * 8);  // per-distance temporaries
+  L.t2 = take((size_t)D * px * 8);
   L.acc = take(px * 8);
   L.v = take(px * 8);
   L.xcur = take(px * 8);
   L.xprev = take(px * 8);
   L.z = take(px * 8);
   L.fgp = take(denoise_ws_bytes(1, m, n));
-  L.part = take((size_t)D * fft_col_blocks(m, n) * 8);
+  L.part = take((size_t)D * residual_blocks(m, n) * 8);
   L.total = o;
   return L;
 }
@@ -71,6 +74,12 @@ ctv_status validate_pr(const pr_params* p, int m, int n, bool need_inner) {
   return CTV_OK;
 }
 
+#define CTV_TRY(expr, what)                            \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, what);   \
+  } while (0)
+
 struct Ctx {
   int m, n, D;
   long long px;
@@ -79,47 +88,95 @@ struct Ctx {
   hipStream_t s;
   float2* at(size_t off) const { return reinterpret_cast<float2*>(ws + off); }
   float* atf(size_t off) const { return reinterpret_cast<float*>(ws + off); }
-  const float2* H(int d) const { return at(L.H) + (size_t)d * px; }
+  const float2* Ht(int d) const { return at(L.H) + (size_t)d * px; }
   const float* sy(int d) const { return atf(L.sy) + (size_t)d * px; }
 };
 
-FftArgs base_args(const Ctx& c) {
+FftArgs line_args(const float2* in, float2* out, const float2* tw, long long stride) {
   FftArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.m = c.m;
-  a.n = c.n;
-  a.img_stride = c.px;
+  a.in = in;
+  a.out = out;
+  a.tw = tw;
+  a.in_stride = stride;
+  a.img_stride = stride;
   a.scale = 1.0f;
+  a.pre = kPreNone;
+  a.post = kPostStore;
   return a;
 }
 
-#define CTV_TRY(expr, what)                   \
-  do {                                        \
-    hipError_t e_ = (expr);                   \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
-
-// out = FFT2(in) (forward) with the column pass finishing as `post`.
-ctv_status fft2_into(const Ctx& c, const float2* in, float2* tmp, int dir, int post, FftArgs tail) {
-  FftArgs r = base_args(c);
-  r.in = in;
-  r.out = tmp;
-  r.tw = c.at(c.L.tw_n);
-  CTV_TRY(launch_fft_rows(r, dir, kPreNone, 1, c.s), "fft rows");
-  tail.in = tmp;
-  tail.tw = c.at(c.L.tw_m);
-  CTV_TRY(launch_fft_cols(tail, dir, post, 1, c.s), "fft cols");
+// Spectrum (transposed, [n][m]) of a natural-layout [m][n] image: a pass along
+// n, a transpose, a pass along m whose epilogue is `last` (in/out/tw filled here).
+ctv_status fft2_to_t(const Ctx& c, const float2* in, float2* out, FftArgs last) {
+  float2* t1 = c.at(c.L.t1);
+  float2* t2 = c.at(c.L.t2);
+  FftArgs a = line_args(in, t1, c.at(c.L.tw_n), c.px);
+  CTV_TRY(launch_fft_lines(a, c.n, c.m, -1, 1, c.s), "fft (rows)");
+  CTV_TRY(launch_transpose(t1, t2, c.m, c.n, 1, c.s), "transpose");
+  last.in = t2;
+  last.out = out;
+  last.tw = c.at(c.L.tw_m);
+  last.in_stride = last.img_stride = c.px;
+  CTV_TRY(launch_fft_lines(last, c.m, c.n, -1, 1, c.s), "fft (columns)");
   return CTV_OK;
 }
 
-// Tables shared by every phase-retrieval entry point: twiddles, H_d, sqrt(y_d).
+// Inverse transform of a transposed spectrum [n][m] to natural layout [m][n]:
+// a pass along m (optionally multiplying by Ht on load), a transpose, and a
+// pass along n with epilogue `last` (scale 1/(mn) folded in by the caller).
+ctv_status ifft2_from_t(const Ctx& c, const float2* in, const float2* Ht, float2* out, FftArgs last) {
+  float2* t1 = c.at(c.L.t1);
+  float2* t2 = c.at(c.L.t2);
+  FftArgs a = line_args(in, t1, c.at(c.L.tw_m), c.px);
+  if (Ht) {
+    a.pre = kPreMulH;
+    a.H = Ht;
+  }
+  CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, 1, c.s), "ifft (columns)");
+  CTV_TRY(launch_transpose(t1, t2, c.n, c.m, 1, c.s), "transpose");
+  last.in = t2;
+  last.out = out;
+  last.tw = c.at(c.L.tw_n);
+  last.in_stride = last.img_stride = c.px;
+  CTV_TRY(launch_fft_lines(last, c.n, c.m, 1, 1, c.s), "ifft (rows)");
+  return CTV_OK;
+}
+
+FftArgs epilogue(int post, float scale) {
+  FftArgs a = line_args(nullptr, nullptr, nullptr, 0);
+  a.post = post;
+  a.scale = scale;
+  return a;
+}
+
+// Tables shared by every phase-retrieval entry point: twiddles, H_d (transposed), sqrt(y_d).
 ctv_status build_tables(const Ctx& c, const pr_params* p, const float* y) {
   CTV_TRY(launch_twiddles(c.at(c.L.tw_n), c.n, c.s), "twiddles");
   CTV_TRY(launch_twiddles(c.at(c.L.tw_m), c.m, c.s), "twiddles");
   for (int d = 0; d < c.D; ++d)
-    CTV_TRY(launch_transfer(c.at(c.L.H) + (size_t)d * c.px, c.m, c.n, p->distances_host[d], p->wavelength,
-                            p->pixel, c.s), "transfer function");
+    CTV_TRY(launch_transfer_t(c.at(c.L.H) + (size_t)d * c.px, c.m, c.n, p->distances_host[d], p->wavelength,
+                              p->pixel, c.s), "transfer function");
   if (y) CTV_TRY(launch_sqrt_y(y, c.atf(c.L.sy), nullptr, (long long)c.D * c.px, c.s), "sqrt(y)");
+  return CTV_OK;
+}
+
+// For every distance at once (batch D): the transposed spectra
+// conj(H_d) * FFT2(r_d) of the natural-layout images r_d (stride px), summed
+// over d into acc inside the last pass.
+ctv_status accumulate_spectra(const Ctx& c, const float2* r, float2* acc) {
+  float2* t1 = c.at(c.L.t1);
+  float2* t2 = c.at(c.L.t2);
+  CTV_TRY(launch_fft_lines(line_args(r, t1, c.at(c.L.tw_n), c.px), c.n, c.m, -1, c.D, c.s), "fft (rows)");
+  CTV_TRY(launch_transpose(t1, t2, c.m, c.n, c.D, c.s), "transpose");
+  FftArgs q = line_args(t2, nullptr, c.at(c.L.tw_m), c.px);
+  q.post = kPostAccumulateAll;
+  q.H = c.Ht(0);
+  q.H_stride = c.px;
+  q.acc = acc;
+  q.accumulate = 0;
+  q.n_acc = c.D;
+  CTV_TRY(launch_fft_lines(q, c.m, c.n, -1, 1, c.s), "fft (columns, accumulate)");
   return CTV_OK;
 }
 
@@ -128,89 +185,88 @@ ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, 
   const float inv = 1.0f / (float)((double)c.m * c.n);
   float2* xh = c.at(c.L.xh);
   float2* t1 = c.at(c.L.t1);
+  float2* t2 = c.at(c.L.t2);
   float2* acc = c.at(c.L.acc);
   double* part = reinterpret_cast<double*>(c.ws + c.L.part);
-  const int cb = fft_col_blocks(c.m, c.n);
-  {  // X = FFT2(z)
-    FftArgs t = base_args(c);
-    t.out = xh;
-    ctv_status st = fft2_into(c, z, t1, -1, kPostStore, t);
-    if (st) return st;
-  }
-  for (int d = 0; d < c.D; ++d) {
-    // A_d z = IFFT2(H_d X), then the residual bracket of Eq. (27)
-    FftArgs r = base_args(c);
-    r.in = xh;
-    r.out = t1;
-    r.tw = c.at(c.L.tw_n);
-    r.H = c.H(d);
-    CTV_TRY(launch_fft_rows(r, 1, kPreMulH, 1, c.s), "fft rows");
-    FftArgs q = base_args(c);
-    q.in = t1;
-    q.out = t1;
-    q.tw = c.at(c.L.tw_m);
-    q.scale = inv;
-    q.sy = c.sy(d);
-    q.partial = part + (size_t)d * cb;
-    CTV_TRY(launch_fft_cols(q, 1, kPostResidual, 1, c.s), "fft cols (residual)");
-    // acc (+)= conj(H_d) FFT2(residual)
-    FftArgs t = base_args(c);
-    t.out = t1;
-    t.H = c.H(d);
-    t.acc = acc;
-    t.accumulate = d > 0;
-    ctv_status st = fft2_into(c, t1, t1, -1, kPostAccumulate, t);
-    if (st) return st;
-  }
-  FftArgs t = base_args(c);
-  t.out = out;
-  t.scale = inv;
-  t.z = z;
-  t.gamma = gamma;
-  ctv_status st = fft2_into(c, acc, t1, 1, post_step ? kPostStep : kPostStore, t);
+  const int rb = residual_blocks(c.m, c.n);
+  ctv_status st = fft2_to_t(c, z, xh, epilogue(kPostStore, 1.0f));
   if (st) return st;
-  if (loss) CTV_TRY(launch_loss_final(part, c.D * cb, loss, c.s), "loss");
+  // A_d z = IFFT2(H_d Z) for all d (one shared input spectrum), then the
+  // residual bracket of Eq. (27) in t2[d]
+  FftArgs a = line_args(xh, t1, c.at(c.L.tw_m), c.px);
+  a.in_stride = 0;
+  a.pre = kPreMulH;
+  a.H = c.Ht(0);
+  a.H_stride = c.px;
+  CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, c.D, c.s), "ifft (columns)");
+  CTV_TRY(launch_transpose(t1, t2, c.n, c.m, c.D, c.s), "transpose");
+  FftArgs r = line_args(t2, t2, c.at(c.L.tw_n), c.px);
+  r.post = kPostResidual;
+  r.scale = inv;
+  r.sy = c.sy(0);
+  r.sy_stride = c.px;
+  r.partial = part;
+  CTV_TRY(launch_fft_lines(r, c.n, c.m, 1, c.D, c.s), "ifft (rows, residual)");
+  // acc = sum_d conj(H_d) FFT2(residual_d)
+  st = accumulate_spectra(c, t2, acc);
+  if (st) return st;
+  FftArgs g = epilogue(post_step ? kPostStep : kPostStore, inv);
+  g.z = z;
+  g.gamma = gamma;
+  st = ifft2_from_t(c, acc, nullptr, out, g);
+  if (st) return st;
+  if (loss) CTV_TRY(launch_loss_final(part, c.D * rb, loss, c.s), "loss");
   return CTV_OK;
+}
+
+Ctx make_ctx(const pr_params* p, int m, int n, void* ws, ctv_stream_t stream) {
+  return Ctx{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
+             reinterpret_cast<hipStream_t>(stream)};
 }
 
 }  // namespace
 
 extern "C" {
 
-ctv_status ctv_fft2_workspace_size(int32_t m, int32_t n, size_t* ws_bytes) {
+ctv_status ctv_fft2_workspace_size(int32_t batch, int32_t m, int32_t n, size_t* ws_bytes) {
+  if (batch < 1) return fail(CTV_ERR_INVALID_ARG, "batch must be >= 1");
   if (!fft_size_ok(m) || !fft_size_ok(n)) return fail(CTV_ERR_UNSUPPORTED, "m and n must be powers of two in [2, 4096]");
   if (!ws_bytes) return fail(CTV_ERR_INVALID_ARG, "ws_bytes is NULL");
-  *ws_bytes = align_up((size_t)n * 8) + align_up((size_t)m * 8);
+  *ws_bytes = align_up((size_t)n * 8) + align_up((size_t)m * 8) + align_up((size_t)batch * m * n * 8);
   return CTV_OK;
 }
 
 ctv_status ctv_fft2(int32_t batch, int32_t m, int32_t n, const float* in, float* out, int32_t inverse, void* ws,
                     size_t ws_bytes, ctv_stream_t stream) {
-  if (batch < 1) return fail(CTV_ERR_INVALID_ARG, "batch must be >= 1");
-  if (!fft_size_ok(m) || !fft_size_ok(n)) return fail(CTV_ERR_UNSUPPORTED, "m and n must be powers of two in [2, 4096]");
+  size_t need = 0;
+  ctv_status st = ctv_fft2_workspace_size(batch, m, n, &need);
+  if (st) return st;
   if (!in || !out || !ws) return fail(CTV_ERR_INVALID_ARG, "in, out and ws must be non-NULL");
-  const size_t need = align_up((size_t)n * 8) + align_up((size_t)m * 8);
   if (ws_bytes < need) return fail(CTV_ERR_WORKSPACE, "workspace too small");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  float2* twn = static_cast<float2*>(ws);
-  float2* twm = reinterpret_cast<float2*>(static_cast<char*>(ws) + align_up((size_t)n * 8));
+  char* w = static_cast<char*>(ws);
+  float2* twn = reinterpret_cast<float2*>(w);
+  float2* twm = reinterpret_cast<float2*>(w + align_up((size_t)n * 8));
+  float2* tmp = reinterpret_cast<float2*>(w + align_up((size_t)n * 8) + align_up((size_t)m * 8));
+  const float2* x = reinterpret_cast<const float2*>(in);
+  float2* y = reinterpret_cast<float2*>(out);
+  const long long px = (long long)m * n;
   CTV_TRY(launch_twiddles(twn, n, s), "twiddles");
   CTV_TRY(launch_twiddles(twm, m, s), "twiddles");
-  const int dir = inverse ? 1 : -1;
-  FftArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.m = m;
-  a.n = n;
-  a.img_stride = (long long)m * n;
-  a.in = reinterpret_cast<const float2*>(in);
-  a.out = reinterpret_cast<float2*>(out);
-  a.tw = twn;
-  a.scale = 1.0f;
-  CTV_TRY(launch_fft_rows(a, dir, kPreNone, batch, s), "fft rows");
-  a.in = reinterpret_cast<const float2*>(out);
-  a.tw = twm;
-  a.scale = inverse ? (float)(1.0 / ((double)m * n)) : 1.0f;
-  CTV_TRY(launch_fft_cols(a, dir, kPostStore, batch, s), "fft cols");
+  if (!inverse) {
+    // rows, transpose, columns (as rows of the transpose), transpose back
+    CTV_TRY(launch_fft_lines(line_args(x, y, twn, px), n, m, -1, batch, s), "fft (rows)");
+    CTV_TRY(launch_transpose(y, tmp, m, n, batch, s), "transpose");
+    CTV_TRY(launch_fft_lines(line_args(tmp, tmp, twm, px), m, n, -1, batch, s), "fft (columns)");
+    CTV_TRY(launch_transpose(tmp, y, n, m, batch, s), "transpose");
+  } else {
+    CTV_TRY(launch_transpose(x, tmp, m, n, batch, s), "transpose");
+    CTV_TRY(launch_fft_lines(line_args(tmp, tmp, twm, px), m, n, 1, batch, s), "ifft (columns)");
+    CTV_TRY(launch_transpose(tmp, y, n, m, batch, s), "transpose");
+    FftArgs a = line_args(y, y, twn, px);
+    a.scale = (float)(1.0 / ((double)m * n));
+    CTV_TRY(launch_fft_lines(a, n, m, 1, batch, s), "ifft (rows)");
+  }
   return CTV_OK;
 }
 
@@ -227,31 +283,23 @@ ctv_status pr_forward(const pr_params* p, int32_t m, int32_t n, const float* x, 
   ctv_status st = validate_pr(p, m, n, false);
   if (st) return st;
   if (!x || !out || !ws) return fail(CTV_ERR_INVALID_ARG, "x, out and ws must be non-NULL");
-  Ctx c{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
-        reinterpret_cast<hipStream_t>(stream)};
+  Ctx c = make_ctx(p, m, n, ws, stream);
   if (ws_bytes < c.L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small");
   st = build_tables(c, p, nullptr);
   if (st) return st;
-  FftArgs t = base_args(c);
-  t.out = c.at(c.L.xh);
-  st = fft2_into(c, reinterpret_cast<const float2*>(x), c.at(c.L.t1), -1, kPostStore, t);
+  st = fft2_to_t(c, reinterpret_cast<const float2*>(x), c.at(c.L.xh), epilogue(kPostStore, 1.0f));
   if (st) return st;
-  const float inv = 1.0f / (float)((double)m * n);
-  for (int d = 0; d < c.D; ++d) {
-    float2* od = reinterpret_cast<float2*>(out) + (size_t)d * c.px;
-    FftArgs r = base_args(c);
-    r.in = c.at(c.L.xh);
-    r.out = od;
-    r.tw = c.at(c.L.tw_n);
-    r.H = c.H(d);
-    CTV_TRY(launch_fft_rows(r, 1, kPreMulH, 1, c.s), "fft rows");
-    FftArgs q = base_args(c);
-    q.in = od;
-    q.out = od;
-    q.tw = c.at(c.L.tw_m);
-    q.scale = inv;
-    CTV_TRY(launch_fft_cols(q, 1, kPostStore, 1, c.s), "fft cols");
-  }
+  float2* o = reinterpret_cast<float2*>(out);
+  FftArgs a = line_args(c.at(c.L.xh), c.at(c.L.t1), c.at(c.L.tw_m), c.px);
+  a.in_stride = 0;
+  a.pre = kPreMulH;
+  a.H = c.Ht(0);
+  a.H_stride = c.px;
+  CTV_TRY(launch_fft_lines(a, m, n, 1, c.D, c.s), "ifft (columns)");
+  CTV_TRY(launch_transpose(c.at(c.L.t1), o, n, m, c.D, c.s), "transpose");
+  FftArgs b = line_args(o, o, c.at(c.L.tw_n), c.px);
+  b.scale = 1.0f / (float)((double)m * n);
+  CTV_TRY(launch_fft_lines(b, n, m, 1, c.D, c.s), "ifft (rows)");
   return CTV_OK;
 }
 
@@ -260,8 +308,7 @@ ctv_status pr_gradient(const pr_params* p, int32_t m, int32_t n, const float* y,
   ctv_status st = validate_pr(p, m, n, false);
   if (st) return st;
   if (!y || !x || !grad || !ws) return fail(CTV_ERR_INVALID_ARG, "y, x, grad and ws must be non-NULL");
-  Ctx c{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
-        reinterpret_cast<hipStream_t>(stream)};
+  Ctx c = make_ctx(p, m, n, ws, stream);
   if (ws_bytes < c.L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small");
   st = build_tables(c, p, y);
   if (st) return st;
@@ -273,8 +320,7 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   ctv_status st = validate_pr(p, m, n, true);
   if (st) return st;
   if (!y || !x || !ws) return fail(CTV_ERR_INVALID_ARG, "y, x and ws must be non-NULL");
-  Ctx c{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
-        reinterpret_cast<hipStream_t>(stream)};
+  Ctx c = make_ctx(p, m, n, ws, stream);
   if (ws_bytes < c.L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small");
   st = build_tables(c, p, y);
   if (st) return st;
@@ -282,26 +328,15 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   float2* xprev = c.at(c.L.xprev);
   float2* z = c.at(c.L.z);
   float2* v = c.at(c.L.v);
-  float2* t1 = c.at(c.L.t1);
   float2* acc = c.at(c.L.acc);
   float2* syc = c.at(c.L.syc);
   const float inv = 1.0f / (float)((double)m * n);
   if (p->init_backprop) {
     // x0 = (1/D) sum_d A_d^H sqrt(y_d): the directly back-propagated field (Section VI-A)
-    for (int d = 0; d < c.D; ++d) {
-      CTV_TRY(launch_sqrt_y(y + (size_t)d * c.px, c.atf(c.L.sy) + (size_t)d * c.px, syc, c.px, c.s), "sqrt(y)");
-      FftArgs t = base_args(c);
-      t.out = t1;
-      t.H = c.H(d);
-      t.acc = acc;
-      t.accumulate = d > 0;
-      st = fft2_into(c, syc, t1, -1, kPostAccumulate, t);
-      if (st) return st;
-    }
-    FftArgs t = base_args(c);
-    t.out = xcur;
-    t.scale = inv / (float)c.D;
-    st = fft2_into(c, acc, t1, 1, kPostStore, t);
+    CTV_TRY(launch_sqrt_y(y, c.atf(c.L.sy), syc, (long long)c.D * c.px, c.s), "sqrt(y)");
+    st = accumulate_spectra(c, syc, acc);
+    if (st) return st;
+    st = ifft2_from_t(c, acc, nullptr, xcur, epilogue(kPostStore, inv / (float)c.D));
     if (st) return st;
   } else {
     CTV_TRY(launch_copy_c(reinterpret_cast<const float2*>(x), xcur, c.px, c.s), "copy");
