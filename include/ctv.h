@@ -61,6 +61,13 @@ typedef int32_t ctv_status;
 #define CTV_C_NONE 0
 #define CTV_C_MODULUS 1
 
+/* Dual iteration: the fast gradient projection (Algorithm 2) or the plain
+ * gradient projection (Eq. 21). Both share the step and the projections; the
+ * plain one drops the momentum (beta_k = 0), converging as O(1/k) instead of
+ * O(1/k^2) in the dual objective. */
+#define CTV_M_FGP 0
+#define CTV_M_GP 1
+
 typedef void* ctv_stream_t; /* hipStream_t */
 
 typedef struct {
@@ -74,6 +81,8 @@ typedef struct {
                            the column-register tile; -1 = the LDS-staged tile (4 waves) */
   int32_t tile_rows;    /* rows per thread: 0 = automatic; column tile 4 or 8 (with waves 4: 8 only);
                            LDS tile 4, 8 or 16 */
+  int32_t method;       /* CTV_M_FGP: Algorithm 2 with the t_k extrapolation; CTV_M_GP: the
+                           unaccelerated gradient projection of Eq. (21), r_k = q_{k-1} */
 } ctv_params;
 
 /* Library version (major*10000 + minor*100 + patch) and last error message. */

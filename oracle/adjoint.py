@@ -95,7 +95,7 @@ def _inner(a, b):
     return float(sum(np.sum(x * y) for x, y in zip(a, b)))
 
 
-def fgp_vjp(b, lam, K, xbar, kind="1i", alpha=0.5, constraint="modulus", mask=None):
+def fgp_vjp(b, lam, K, xbar, kind="1i", alpha=0.5, constraint="modulus", mask=None, method="fgp"):
     """Returns (x, bbar complex, lambar float) for loss gradient xbar (complex,
     real-pair convention)."""
     b = np.asarray(b, dtype=np.complex128)
@@ -107,8 +107,9 @@ def fgp_vjp(b, lam, K, xbar, kind="1i", alpha=0.5, constraint="modulus", mask=No
         return pu + 1j * pv, bu + 1j * bv, 0.0
     t = _tv.t_sequence(K + 1)
     beta = np.zeros(K + 1)              # beta[k] = (t_k - 1)/t_{k+1}, beta[0] = 0
-    for k in range(1, K + 1):
-        beta[k] = (t[k] - 1.0) / t[k + 1]
+    if method == "fgp":
+        for k in range(1, K + 1):
+            beta[k] = (t[k] - 1.0) / t[k + 1]
     c = 1.0 / (8.0 * lam)
     # forward, keeping every iterate
     qs = [_tv.zeros_dual(m, n)]

@@ -71,8 +71,9 @@ def backprop(sqrt_y, Hs):
 
 
 def fista(y, distances, wavelength, pixel, outer, inner, tau, gamma,
-          kind="1i", alpha=0.5, constraint="modulus", x0=None, accelerate=True):
-    """Algorithm 1 with prox_{gamma R} = FGP (Algorithm 2) at lam = tau*gamma.
+          kind="1i", alpha=0.5, constraint="modulus", x0=None, accelerate=True, inner_method="fgp"):
+    """Algorithm 1 with prox_{gamma R} = FGP (Algorithm 2) at lam = tau*gamma
+    (inner_method="gp": the unaccelerated prox iteration of Eq. 21).
 
     y: (D, m, n) intensities. Returns (x_K, loss) where loss[k-1] = F(z_k), the
     data term at the k-th gradient point. accelerate=False gives the plain
@@ -90,7 +91,7 @@ def fista(y, distances, wavelength, pixel, outer, inner, tau, gamma,
     for _ in range(outer):
         loss.append(data_term(z, sqrt_y, Hs))
         v = z - gamma * grad_F(z, sqrt_y, Hs)
-        x = _tv.fgp(v, lam, inner, kind, alpha, constraint)
+        x = _tv.fgp(v, lam, inner, kind, alpha, constraint, method=inner_method)
         t_new = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
         beta = (t - 1.0) / t_new if accelerate else 0.0
         z = x + beta * (x - x_prev)

@@ -55,10 +55,10 @@ def _project_dual(pp, qq, iso, radius):
     return pp, qq
 
 
-def real_fgp(b, lam, K, iso=True, lo=-1.0, hi=1.0, radius=1.0):
-    """K iterations of the real constrained FGP; returns (x, p, q) where p, q
-    are the unpadded vertical / horizontal duals scaled to the unit ball
-    (divided by ``radius``).
+def real_fgp(b, lam, K, iso=True, lo=-1.0, hi=1.0, radius=1.0, accelerate=True):
+    """K iterations of the real constrained FGP (accelerate=False: the plain
+    gradient projection); returns (x, p, q) where p, q are the unpadded
+    vertical / horizontal duals.
 
     ``radius`` lets the same routine express a dual set scaled by alpha: with
     radius alpha and weight lam the iterates are alpha times those of radius 1
@@ -76,7 +76,7 @@ def real_fgp(b, lam, K, iso=True, lo=-1.0, hi=1.0, radius=1.0):
         z = np.clip(b - lam * _div(rp, rq), lo, hi)
         dp, dq = _diffs(z, ps, qs)
         p, q = _project_dual(rp + step * dp, rq + step * dq, iso, radius)
-        t_new = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        t_new = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0 if accelerate else 1.0
         c = (t - 1.0) / t_new
         rp = p + c * (p - p_old)
         rq = q + c * (q - q_old)

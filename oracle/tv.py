@@ -238,8 +238,9 @@ def primal_from_dual(q, b, lam, constraint="modulus", mask=None):
 
 
 def fgp(b, lam, K, kind="1i", alpha=0.5, constraint="modulus", mask=None,
-        state=None, return_state=False):
-    """Algorithm 2 followed by Eq. (18).
+        state=None, return_state=False, method="fgp"):
+    """Algorithm 2 followed by Eq. (18); method="gp" runs the basic gradient
+    projection of Eq. (21) instead (the same step with no extrapolation).
 
     b: complex array (upcast to complex128). Runs K iterations. ``state`` =
     (q_k, q_{k-1}, k) resumes from iteration k (t_k follows from k alone).
@@ -259,7 +260,11 @@ def fgp(b, lam, K, kind="1i", alpha=0.5, constraint="modulus", mask=None,
         yu, yv = P_C(b.real, b.imag, constraint, mask)
         x = yu + 1j * yv
         return (x, (q, q_prev, k0 + K)) if return_state else x
+    if method not in ("fgp", "gp"):
+        raise ValueError(method)
     t = t_sequence(k0 + K + 1)
+    if method == "gp":
+        t[:] = 1.0                          # Eq. (21): r_k = q_{k-1}
     # r_{k0+1} = q_{k0} + ((t_{k0} - 1)/t_{k0+1}) (q_{k0} - q_{k0-1}); at k0 = 0 it is q_0.
     beta = (t[k0] - 1.0) / t[k0 + 1] if k0 >= 1 else 0.0
     r = tuple(a + beta * (a - c) for a, c in zip(q, q_prev))

@@ -49,9 +49,9 @@ def tiling(fuse=0, iters=100, m=2048, n=2048, batch=1, tile=(0, 0), detail=False
 
 
 def workspace_size(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0,
-                   ckpt_every=0):
+                   ckpt_every=0, method="fgp"):
     """(workspace bytes, checkpoint bytes) for ``denoise``."""
-    p = make_params(kind, alpha, constraint, iters, fuse)
+    p = make_params(kind, alpha, constraint, iters, fuse, method=method)
     ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
     call("ctv_workspace_size", ctypes.byref(p), batch, m, n, ckpt_every, ctypes.byref(ws), ctypes.byref(sv))
     return ws.value, sv.value
@@ -59,26 +59,27 @@ def workspace_size(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", it
 
 def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, iters=100, fuse=0,
             gap=False, state=None, k0=0, return_state=False, ckpt_every=0, saved=None, out=None,
-            workspace=None, tile=(0, 0)):
+            workspace=None, tile=(0, 0), method="fgp"):
     """K FGP iterations (Algorithm 2) + Eq. (18) on the GPU.
 
     b: complex64 CUDA tensor [m, n] or [B, m, n]. lam: float or B floats.
-    support: uint8 [m, n] or None. Returns x (and the duality gap as a float64
-    tensor [B] when gap=True, and the dual state when return_state=True).
+    support: uint8 [m, n] or None. method: "fgp" (Algorithm 2) or "gp" (the
+    unaccelerated iteration of Eq. 21). Returns x (and the duality gap as a
+    float64 tensor [B] when gap=True, and the dual state when return_state=True).
     """
     _require_cuda(b, "b", torch.complex64)
     squeeze = b.dim() == 2
     bb = b.unsqueeze(0) if squeeze else b
     B, m, n = bb.shape
     dev = bb.device
-    p = make_params(kind, alpha, constraint, iters, fuse, tile)
+    p = make_params(kind, alpha, constraint, iters, fuse, tile, method)
     if support is not None:
         _require_cuda(support, "support", torch.uint8)
         if tuple(support.shape) != (m, n):
             raise ValueError("support must be [m, n]")
     x = out if out is not None else torch.empty_like(bb)
     _require_cuda(x, "out", torch.complex64)
-    ws_bytes, sv_bytes = workspace_size(m, n, B, kind, alpha, constraint, iters, fuse, ckpt_every)
+    ws_bytes, sv_bytes = workspace_size(m, n, B, kind, alpha, constraint, iters, fuse, ckpt_every, method)
     ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     g = torch.empty(B, dtype=torch.float64, device=dev) if gap else None
     st_out = torch.empty((B, 2, m, n, 4), dtype=torch.float32, device=dev) if return_state else None
@@ -101,7 +102,7 @@ def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, it
 
 
 def denoise_backward(b, lam, grad_x, saved, kind="1i", alpha=0.5, constraint="modulus", support=None,
-                     iters=100, fuse=0, ckpt_every=10):
+                     iters=100, fuse=0, ckpt_every=10, method="fgp"):
     """Reverse pass of the K-step map; returns (grad_b, grad_lambda[B])."""
     _require_cuda(b, "b", torch.complex64)
     _require_cuda(grad_x, "grad_x", torch.complex64)
@@ -110,7 +111,7 @@ def denoise_backward(b, lam, grad_x, saved, kind="1i", alpha=0.5, constraint="mo
     gx = grad_x.unsqueeze(0) if squeeze else grad_x
     B, m, n = bb.shape
     dev = bb.device
-    p = make_params(kind, alpha, constraint, iters, fuse)
+    p = make_params(kind, alpha, constraint, iters, fuse, method=method)
     ws_bytes = ctypes.c_size_t()
     call("ctv_backward_workspace_size", ctypes.byref(p), B, m, n, ckpt_every, ctypes.byref(ws_bytes))
     ws = torch.empty(ws_bytes.value, dtype=torch.uint8, device=dev)
@@ -125,36 +126,36 @@ def denoise_backward(b, lam, grad_x, saved, kind="1i", alpha=0.5, constraint="mo
 class CTVDenoise(torch.autograd.Function):
     """x = FGP_K(b, lambda) with gradients for b (complex64) and lambda.
 
-    apply(b, lam, kind, alpha, constraint, support, iters, ckpt_every, fuse).
+    apply(b, lam, kind, alpha, constraint, support, iters, ckpt_every, fuse, method).
     lam may be a Python float (no gradient) or a float32 tensor of shape [] or
     [B]; a scalar tensor receives the sum of the per-image gradients.
     """
 
     @staticmethod
     def forward(ctx, b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, iters=50,
-                ckpt_every=10, fuse=0):
+                ckpt_every=10, fuse=0, method="fgp"):
         lam_vals = lam.detach() if isinstance(lam, torch.Tensor) else lam
         x, saved = denoise(b, lam_vals, kind, alpha, constraint, support, iters, fuse,
-                           ckpt_every=ckpt_every)
+                           ckpt_every=ckpt_every, method=method)
         ctx.save_for_backward(b, saved)
         ctx.lam = lam_vals.cpu().reshape(-1).tolist() if isinstance(lam_vals, torch.Tensor) else lam_vals
         ctx.lam_shape = lam.shape if isinstance(lam, torch.Tensor) else None
         ctx.lam_meta = (lam.device, lam.dtype) if isinstance(lam, torch.Tensor) else None
-        ctx.cfg = (kind, alpha, constraint, support, iters, fuse, ckpt_every)
+        ctx.cfg = (kind, alpha, constraint, support, iters, fuse, ckpt_every, method)
         return x
 
     @staticmethod
     def backward(ctx, grad_x):
         b, saved = ctx.saved_tensors
-        kind, alpha, constraint, support, iters, fuse, ckpt_every = ctx.cfg
+        kind, alpha, constraint, support, iters, fuse, ckpt_every, method = ctx.cfg
         gb, gl = denoise_backward(b, ctx.lam, grad_x.contiguous(), saved, kind, alpha, constraint, support,
-                                  iters, fuse, ckpt_every)
+                                  iters, fuse, ckpt_every, method)
         glam = None
         if ctx.lam_shape is not None:
             glam = gl.sum().reshape(ctx.lam_shape) if len(ctx.lam_shape) == 0 or ctx.lam_shape.numel() == 1 \
                 else gl.reshape(ctx.lam_shape)
             glam = glam.to(device=ctx.lam_meta[0], dtype=ctx.lam_meta[1])
-        return gb, glam, None, None, None, None, None, None, None
+        return gb, glam, None, None, None, None, None, None, None, None
 
 
 class BatchedPlan:
@@ -165,7 +166,7 @@ class BatchedPlan:
     order given; ``offsets`` gives each image's first pixel.
     """
 
-    def __init__(self, images, constraint="modulus", fuse=0):
+    def __init__(self, images, constraint="modulus", fuse=0, method="fgp"):
         descs = (_lib.ImageDesc * len(images))()
         off = 0
         soff = 0
@@ -190,7 +191,7 @@ class BatchedPlan:
             off += m * n
         self.total_pixels = off
         self.support_bytes = soff
-        common = make_params("1i", 0.5, constraint, 0, fuse)
+        common = make_params("1i", 0.5, constraint, 0, fuse, method=method)
         h = ctypes.c_void_p()
         call("ctv_batched_plan_create", descs, len(images), ctypes.byref(common), ctypes.byref(h))
         self._h = h
@@ -240,10 +241,11 @@ class BatchedPlan:
 
 
 def _pr_params(distances, wavelength, pixel, tau, gamma, outer, inner_iters, kind, alpha, constraint,
-               init_backprop, accelerate, fuse):
+               init_backprop, accelerate, fuse, inner_method="fgp"):
     dist = (ctypes.c_double * len(distances))(*[float(d) for d in distances])
     p = _lib.PrParams(ctypes.sizeof(_lib.PrParams), len(distances), dist, float(wavelength), float(pixel),
-                      float(tau), float(gamma), int(outer), make_params(kind, alpha, constraint, inner_iters, fuse),
+                      float(tau), float(gamma), int(outer), make_params(kind, alpha, constraint, inner_iters, fuse,
+                                                                     method=inner_method),
                       int(init_backprop), int(accelerate))
     return p, dist
 
@@ -255,13 +257,15 @@ def _pr_ws(p, m, n, dev):
 
 
 def phase_retrieval(y, distances, wavelength, pixel, tau=0.01, gamma=0.0, outer=100, inner=20, kind="1i",
-                    alpha=0.5, constraint="modulus", x0=None, accelerate=True, fuse=0, loss=False):
-    """Algorithm 1 with the FGP prox; y: float32 CUDA [D, m, n] intensities."""
+                    alpha=0.5, constraint="modulus", x0=None, accelerate=True, fuse=0, loss=False,
+                    inner_method="fgp"):
+    """Algorithm 1 with the FGP prox (inner_method "gp": the Eq. 21 prox);
+    y: float32 CUDA [D, m, n] intensities."""
     _require_cuda(y, "y", torch.float32)
     D, m, n = y.shape
     dev = y.device
     p, _keep = _pr_params(distances, wavelength, pixel, tau, gamma, outer, inner, kind, alpha, constraint,
-                          x0 is None, accelerate, fuse)
+                          x0 is None, accelerate, fuse, inner_method)
     x = torch.empty((m, n), dtype=torch.complex64, device=dev) if x0 is None else x0.clone()
     lt = torch.empty(max(outer, 1), dtype=torch.float32, device=dev) if loss else None
     ws = _pr_ws(p, m, n, dev)

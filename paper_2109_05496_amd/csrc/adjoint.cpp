@@ -101,7 +101,7 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
   if (st) return st;
   tl.T = 1;
   std::vector<float> beta;
-  momentum_table(K + 1, beta);
+  momentum_table(p->method, K + 1, beta);
   const int tiles_x = adj_tiles_x(n), tiles_per_img = tiles_x * adj_tiles_y(m);
 
   for (int c0 = 0; c0 < batch; c0 += kPlainChunk) {

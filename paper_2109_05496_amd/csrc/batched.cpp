@@ -193,7 +193,7 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
     return fail(CTV_ERR_INVALID_ARG, "batch too large");
   }
   std::vector<float> beta;
-  momentum_table(steps * T + kMaxFuse + 1, beta);
+  momentum_table(common->method, steps * T + kMaxFuse + 1, beta);
 
   hipError_t e = hipMalloc(&p->d_images, imgs.size() * sizeof(BatchImage));
   if (e == hipSuccess) e = hipMalloc(&p->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile));

@@ -36,6 +36,7 @@ ctv_status validate_params(const ctv_params* p) {
   if (!(p->alpha >= 0.0f && p->alpha <= 1.0f)) return fail(CTV_ERR_INVALID_ARG, "alpha must lie in [0, 1]");
   if (p->iters < 0) return fail(CTV_ERR_INVALID_ARG, "iters must be >= 0");
   if (p->fuse < 0 || p->fuse > kMaxFuse) return fail(CTV_ERR_INVALID_ARG, "fuse must lie in [0, 16]");
+  if (p->method != CTV_M_FGP && p->method != CTV_M_GP) return fail(CTV_ERR_INVALID_ARG, "unknown method");
   return CTV_OK;
 }
 
@@ -58,10 +59,12 @@ Radii make_radii(int kind, float alpha) {
   return R;
 }
 
-void momentum_table(int kmax, std::vector<float>& beta) {
+void momentum_table(int method, int kmax, std::vector<float>& beta) {
   // beta[k] = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
-  // (Algorithm 2, lines 4-5), evaluated in float64 and rounded once.
+  // (Algorithm 2, lines 4-5), evaluated in float64 and rounded once. The plain
+  // gradient projection (Eq. 21) keeps every beta at 0: r_k = q_{k-1} exactly.
   beta.assign((size_t)kmax + 2, 0.0f);
+  if (method == CTV_M_GP) return;
   double t = 1.0;
   for (int k = 1; k <= kmax + 1; ++k) {
     const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
@@ -228,7 +231,7 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
   st = choose_tiling(p, m, n, batch, &tl);
   if (st) return st;
   std::vector<float> beta;
-  momentum_table(k0 + p->iters + 1, beta);
+  momentum_table(p->method, k0 + p->iters + 1, beta);
   const Radii R = make_radii(p->tv_kind, p->alpha);
 
   for (int c0 = 0; c0 < batch; c0 += kPlainChunk) {

@@ -21,7 +21,7 @@ ctv_status hip_fail(hipError_t e, const char* where);
 ctv_status validate_params(const ctv_params* p);
 ctv_status validate_lambda(float lam);
 Radii make_radii(int kind, float alpha);
-void momentum_table(int kmax, std::vector<float>& beta);
+void momentum_table(int method, int kmax, std::vector<float>& beta);
 float step_of(float lam);
 ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out);
 size_t state_bytes(long long batch, long long m, long long n);

@@ -350,7 +350,7 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   if (st) return st;
   const int Kin = p->inner.iters;
   std::vector<float> beta;
-  momentum_table(Kin + 1, beta);
+  momentum_table(p->inner.method, Kin + 1, beta);
   float* fws = reinterpret_cast<float*>(c.ws + c.L.fgp);
   const size_t st_floats = state_bytes(1, m, n) / 4;
   float* fA = fws;

@@ -74,6 +74,11 @@ def test_unknown_enums_and_struct_size():
     p = P()
     p.struct_size = 4
     assert denoise_status(p) == INVALID
+    p = P()
+    p.method = 2
+    assert denoise_status(p) == INVALID
+    with pytest.raises(ValueError):
+        _lib.make_params(method="newton")
 
 
 def test_workspace_too_small():

@@ -29,7 +29,7 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def gpu_vjp(b, lam, K, xbar, kind, alpha=0.5, constraint="modulus", mask=None, ckpt=10):
+def gpu_vjp(b, lam, K, xbar, kind, alpha=0.5, constraint="modulus", mask=None, ckpt=10, method="fgp"):
     """Always runs a batch (a single image becomes a batch of one)."""
     if b.ndim == 2:
         b, xbar = b[None], xbar[None]
@@ -37,9 +37,9 @@ def gpu_vjp(b, lam, K, xbar, kind, alpha=0.5, constraint="modulus", mask=None, c
     lams = lam if isinstance(lam, (list, tuple)) else [lam]
     mk = None if mask is None else dev(mask)
     x, saved = ctv().denoise(bt, lams, kind=kind, alpha=alpha, constraint=constraint, support=mk, iters=K,
-                             ckpt_every=ckpt)
+                             ckpt_every=ckpt, method=method)
     gb, gl = ctv().denoise_backward(bt, lams, dev(xbar.astype(np.complex64)), saved, kind=kind, alpha=alpha,
-                                    constraint=constraint, support=mk, iters=K, ckpt_every=ckpt)
+                                    constraint=constraint, support=mk, iters=K, ckpt_every=ckpt, method=method)
     torch.cuda.synchronize()
     return x.cpu().numpy(), gb.cpu().numpy(), gl.cpu().numpy()
 
@@ -139,3 +139,13 @@ def test_config4_full_batch_against_finite_differences():
     fd_l = (f(b64, c["lam"] + h) - f(b64, c["lam"] - h)) / (2 * h)
     print("config4 d/dlambda: FD", fd_l, "GPU adjoint", gl)
     assert abs(gl - fd_l) <= TOL * abs(fd_l)
+
+
+@pytest.mark.parametrize("kind", ["1i", "2a"])
+def test_backward_gradient_projection_method(kind):
+    b, xbar = case((52, 67), 12)
+    _, gb, gl = gpu_vjp(b, 0.08, 21, xbar, kind, 0.4, ckpt=6, method="gp")
+    _, gbo, glo = oadj.fgp_vjp(b.astype(np.complex128), 0.08, 21, xbar.astype(np.complex128), kind, 0.4,
+                               method="gp")
+    assert rel(gb[0], gbo) <= TOL
+    assert abs(gl[0] - glo) <= TOL * max(1.0, abs(glo))

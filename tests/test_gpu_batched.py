@@ -96,3 +96,22 @@ def test_config3_full_batch_matches_plain_calls():
         xo = tv.fgp(d["b"].astype(np.complex128), d["lam"], d["iters"], d["kind"])
         assert rel(out[i].cpu().numpy(), xo) <= 1e-5, i
     plan.close()
+
+
+def test_batched_gradient_projection_method():
+    imgs, bs, masks = awkward_batch(seed=3)
+    plan = ctv().BatchedPlan(imgs, method="gp")
+    out = plan.unpack(plan.run(plan.pack(bs), plan.pack_support(masks)))
+    torch.cuda.synchronize()
+    mit = iter(masks)
+    for i, (d, b) in enumerate(zip(imgs, bs)):
+        mask = next(mit) if d["has_support"] else None
+        ref = ctv().denoise(torch.as_tensor(b).cuda(), d["lam"], kind=d["kind"], alpha=d["alpha"],
+                            iters=d["iters"], support=None if mask is None else torch.as_tensor(mask).cuda(),
+                            method="gp").cpu().numpy()
+        x = out[i].cpu().numpy()
+        assert np.array_equal(x.view(np.uint32), ref.view(np.uint32)), i
+        xo = tv.fgp(b.astype(np.complex128), d["lam"], d["iters"], d["kind"], d["alpha"], "modulus", mask,
+                    method="gp")
+        assert rel(x, xo) <= 1e-5, (i, rel(x, xo))
+    plan.close()

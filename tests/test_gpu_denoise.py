@@ -163,3 +163,27 @@ def test_tile_shapes_are_bitwise_invisible(kind):
             assert np.array_equal(x.view(np.uint32), ref.view(np.uint32)), (tile, fuse)
     xo = tv.fgp(b.astype(np.complex128), 0.09, 17, kind, 0.5, "modulus", mask)
     assert rel(ref, xo) <= TOL
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_gradient_projection_method_matches_oracle(kind):
+    """Eq. (21) (no extrapolation): same kernels with every beta = 0; matches
+    the oracle's GP, differs from FGP, and resumes bit for bit."""
+    rng = np.random.default_rng(31)
+    b = (case((83, 131), 14) * 1.4).astype(np.complex64)
+    mask = synth.square_mask(83, 131, 0.7, rng)
+    x = ctv().denoise(dev(b), 0.08, kind=kind, iters=26, support=dev(mask), method="gp").cpu().numpy()
+    xo = tv.fgp(b.astype(np.complex128), 0.08, 26, kind, 0.5, "modulus", mask, method="gp")
+    assert rel(x, xo) <= TOL
+    assert rel(x, xo) <= GUARD
+    xf = ctv().denoise(dev(b), 0.08, kind=kind, iters=26, support=dev(mask)).cpu().numpy()
+    assert rel(xf, x) > 1e-4
+    _, st = ctv().denoise(dev(b), 0.08, kind=kind, iters=9, support=dev(mask), method="gp", return_state=True)
+    x2 = ctv().denoise(dev(b), 0.08, kind=kind, iters=17, support=dev(mask), method="gp", state=st,
+                       k0=9).cpu().numpy()
+    assert np.array_equal(x2.view(np.uint32), x.view(np.uint32))
+
+
+def test_unknown_method_is_rejected():
+    with pytest.raises(ValueError):
+        ctv().denoise(dev(case((8, 8), 1)), 0.1, method="newton")

@@ -89,6 +89,16 @@ def test_ista_variant_matches_oracle():
     assert rel(x.cpu().numpy(), xo) <= 1e-4
 
 
+def test_gp_prox_variant_matches_oracle():
+    truth, Hs, y = small_problem(m=64, D=2, seed=6)
+    dists = P5["distances"][:2]
+    x = ctv().phase_retrieval(dev(y), dists, P5["wavelength"], P5["pixel"], tau=0.02, gamma=0.5, outer=2, inner=6,
+                              kind="1a", inner_method="gp")
+    xo, _ = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 2, 6, 0.02, 0.5, "1a",
+                      inner_method="gp")
+    assert rel(x.cpu().numpy(), xo) <= 1e-4
+
+
 def test_config5_full_run():
     """1024^2 object, 4 distances, Poisson 1000 photons, 100 outer x 20 inner:
     the first outer iteration equals the oracle's to 1e-5; over the full run the

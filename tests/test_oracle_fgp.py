@@ -213,3 +213,21 @@ def test_paper_qualitative_regularisation_strength():
     out = {k: tv.tv(tv.fgp(b, lam, f1["iters"], k, f1["alpha"]), "1i") for k in tv.KINDS}
     assert out["1i"] < out["2i"] and out["1a"] < out["2a"]
     assert out["1a"] < out["1i"] and out["2a"] < out["2i"]
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_gradient_projection_variant(kind, rng):
+    """Eq. (21): the unaccelerated iteration equals the independent real solver
+    with acceleration off, differs from FGP at equal K, and reaches the same
+    minimiser (brute-force certificate)."""
+    b = rng.standard_normal((6, 7)) * 1.3
+    lam, K = 0.15, 40
+    x = tv.fgp(b + 0j, lam, K, kind, 0.5, method="gp")
+    xr, _, _ = real_fgp.real_fgp(b, lam if kind[0] == "1" else lam * 0.5, K, iso=kind.endswith("i"),
+                                 accelerate=False)
+    np.testing.assert_allclose(x.real, xr, atol=1e-13)
+    bc = rand_img((4, 4), rng, 0.9)
+    xg, (q, _, _) = tv.fgp(bc, 0.3, 20000, kind, method="gp", return_state=True)
+    prob = pdhg.Problem(bc, 0.3, kind, 0.5)
+    assert prob.certificate(pdhg.to_vec(xg), pdhg.dual_to_vec(q, 0.3)) <= 1e-10
+    assert np.abs(tv.fgp(bc, 0.3, 15, kind, method="gp") - tv.fgp(bc, 0.3, 15, kind)).max() > 1e-6
