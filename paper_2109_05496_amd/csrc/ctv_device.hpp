@@ -41,35 +41,55 @@ __device__ __forceinline__ float2 proj_c(float2 w, bool inside) {
   return y;
 }
 
-// P_S of one pixel's dual group(s).
+// P_S of one pixel's dual group(s), as the scale applied to each entry of g:
 //   1i: the 4-vector onto the unit ball (Eq. 20)
 //   1a: each complex direction pair onto the unit disc (Eq. 33)
 //   2i: (r1, r2) onto the alpha-disc, (s1, s2) onto the (1-alpha)-disc (Eq. 35)
-//   2a: each real entry clipped to [-alpha, alpha] or [-(1-alpha), 1-alpha] (Eq. 37)
 // Each scale is min(1, radius / norm), i.e. the paper's radius / max{radius, norm}.
+// Type 2a (Eq. 37) clips each real entry to [-alpha, alpha] or
+// [-(1-alpha), 1-alpha] instead and has no scale form.
 template <int KIND>
-__device__ __forceinline__ float4 proj_s(float4 g, const Radii& R) {
+__device__ __forceinline__ float4 ps_scale(float4 g, const Radii& R) {
   if (KIND == K1I) {
     const float n2 = fmaf(g.x, g.x, fmaf(g.y, g.y, fmaf(g.z, g.z, g.w * g.w)));
     const float s = fminf(1.0f, rsq(n2));
-    return make_float4(g.x * s, g.y * s, g.z * s, g.w * s);
+    return make_float4(s, s, s, s);
   } else if (KIND == K1A) {
     const float n1 = fmaf(g.x, g.x, g.y * g.y);
     const float n2 = fmaf(g.z, g.z, g.w * g.w);
     const float s1 = fminf(1.0f, rsq(n1));
     const float s2 = fminf(1.0f, rsq(n2));
-    return make_float4(g.x * s1, g.y * s1, g.z * s2, g.w * s2);
-  } else if (KIND == K2I) {
+    return make_float4(s1, s1, s2, s2);
+  } else {
     // rho / max{rho, ||v||} = min(1, rho / ||v||); a zero radius gives 0 * inf = NaN
     // at v = 0, which fminf turns into 1, and 0 * v = 0 either way.
     const float nr = fmaf(g.x, g.x, g.z * g.z);
     const float ns = fmaf(g.y, g.y, g.w * g.w);
     const float fr = fminf(1.0f, R.ra * rsq(nr));
     const float fs = fminf(1.0f, R.sa * rsq(ns));
-    return make_float4(g.x * fr, g.y * fs, g.z * fr, g.w * fs);
+    return make_float4(fr, fs, fr, fs);
+  }
+}
+
+// One dual update in place: q <- P_S(g) (q_k of Algorithm 2, line 4) and
+// r <- q_k + beta_k (q_k - q_{k-1}) (line 5), with q holding q_{k-1} on entry.
+// For the scaled kinds the difference d = s g - q_{k-1} is formed with one
+// fused multiply-add and q_k = q_{k-1} + d, so the update touches q's
+// registers in place (three operations per entry; within a rounding of s g).
+template <int KIND>
+__device__ __forceinline__ void dual_update(float4 g, const Radii& R, float beta, float4& q, float4& r) {
+  if (KIND == K2A) {
+    const float4 qn = make_float4(fminf(fmaxf(g.x, -R.ra), R.ra), fminf(fmaxf(g.y, -R.sa), R.sa),
+                                  fminf(fmaxf(g.z, -R.ra), R.ra), fminf(fmaxf(g.w, -R.sa), R.sa));
+    r = make_float4(fmaf(beta, qn.x - q.x, qn.x), fmaf(beta, qn.y - q.y, qn.y),
+                    fmaf(beta, qn.z - q.z, qn.z), fmaf(beta, qn.w - q.w, qn.w));
+    q = qn;
   } else {
-    return make_float4(fminf(fmaxf(g.x, -R.ra), R.ra), fminf(fmaxf(g.y, -R.sa), R.sa),
-                       fminf(fmaxf(g.z, -R.ra), R.ra), fminf(fmaxf(g.w, -R.sa), R.sa));
+    const float4 s = ps_scale<KIND>(g, R);
+    const float dx = fmaf(g.x, s.x, -q.x), dy = fmaf(g.y, s.y, -q.y);
+    const float dz = fmaf(g.z, s.z, -q.z), dw = fmaf(g.w, s.w, -q.w);
+    q = make_float4(q.x + dx, q.y + dy, q.z + dz, q.w + dw);
+    r = make_float4(fmaf(beta, dx, q.x), fmaf(beta, dy, q.y), fmaf(beta, dz, q.z), fmaf(beta, dw, q.w));
   }
 }
 
@@ -97,12 +117,6 @@ __device__ __forceinline__ float4 dual_step(float4 r, float2 y, float2 down, flo
   g.z = has_right ? fmaf(c, y.x - right.x, r.z) : 0.0f;
   g.w = has_right ? fmaf(c, y.y - right.y, r.w) : 0.0f;
   return g;
-}
-
-// r_{k+1} = q_k + beta_k (q_k - q_{k-1})  (Algorithm 2, line 5).
-__device__ __forceinline__ float4 extrapolate(float4 qn, float4 qo, float beta) {
-  return make_float4(fmaf(beta, qn.x - qo.x, qn.x), fmaf(beta, qn.y - qo.y, qn.y),
-                     fmaf(beta, qn.z - qo.z, qn.z), fmaf(beta, qn.w - qo.w, qn.w));
 }
 
 // Consecutive workgroup ids are spread round-robin over the 8 XCDs of an

@@ -103,9 +103,7 @@ __device__ __forceinline__ void fgp_tile(const TileJob& J, const int H, const fl
       const float2 down = sY[(ry < RH - 1 ? ry + 1 : RH - 1) * kRW + lane];
       const float2 right = sY[ry * kRW + (lane < kRW - 1 ? lane + 1 : kRW - 1)];
       const float4 g = dual_step(r[i], y[i], down, right, J.c, j < J.m - 1, has_right);
-      const float4 qn = proj_s<KIND>(g, J.R);
-      r[i] = extrapolate(qn, q[i], beta);
-      q[i] = qn;
+      dual_update<KIND>(g, J.R, beta, q[i], r[i]);
     }
   }
 
@@ -247,9 +245,7 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
         const float2 down = (i < P - 1) ? y[i + 1] : down_last;
         const float4 g = dual_step(r[i], y[i], down, make_float2(rx, rv), J.c,
                                    !BORDER || j < J.m - 1, has_right);
-        const float4 qn = proj_s<KIND>(g, J.R);
-        r[i] = extrapolate(qn, q[i], beta);
-        q[i] = qn;
+        dual_update<KIND>(g, J.R, beta, q[i], r[i]);
       }
     }
   }
