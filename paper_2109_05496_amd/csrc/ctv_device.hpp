@@ -73,24 +73,27 @@ __device__ __forceinline__ float4 ps_scale(float4 g, const Radii& R) {
 
 // One dual update in place: q <- P_S(g) (q_k of Algorithm 2, line 4) and
 // r <- q_k + beta_k (q_k - q_{k-1}) (line 5), with q holding q_{k-1} on entry.
-// For the scaled kinds the difference d = s g - q_{k-1} is formed with one
-// fused multiply-add and q_k = q_{k-1} + d, so the update touches q's
-// registers in place (three operations per entry; within a rounding of s g).
+// The difference d = P_S(g) - q_{k-1} is formed first (one fused multiply-add
+// per entry for the scaled kinds) and q_k = q_{k-1} + d, so the update writes
+// q's registers in place: three operations per entry, and q_k within a
+// rounding of P_S(g).
 template <int KIND>
 __device__ __forceinline__ void dual_update(float4 g, const Radii& R, float beta, float4& q, float4& r) {
+  float dx, dy, dz, dw;
   if (KIND == K2A) {
-    const float4 qn = make_float4(fminf(fmaxf(g.x, -R.ra), R.ra), fminf(fmaxf(g.y, -R.sa), R.sa),
-                                  fminf(fmaxf(g.z, -R.ra), R.ra), fminf(fmaxf(g.w, -R.sa), R.sa));
-    r = make_float4(fmaf(beta, qn.x - q.x, qn.x), fmaf(beta, qn.y - q.y, qn.y),
-                    fmaf(beta, qn.z - q.z, qn.z), fmaf(beta, qn.w - q.w, qn.w));
-    q = qn;
+    dx = fminf(fmaxf(g.x, -R.ra), R.ra) - q.x;
+    dy = fminf(fmaxf(g.y, -R.sa), R.sa) - q.y;
+    dz = fminf(fmaxf(g.z, -R.ra), R.ra) - q.z;
+    dw = fminf(fmaxf(g.w, -R.sa), R.sa) - q.w;
   } else {
     const float4 s = ps_scale<KIND>(g, R);
-    const float dx = fmaf(g.x, s.x, -q.x), dy = fmaf(g.y, s.y, -q.y);
-    const float dz = fmaf(g.z, s.z, -q.z), dw = fmaf(g.w, s.w, -q.w);
-    q = make_float4(q.x + dx, q.y + dy, q.z + dz, q.w + dw);
-    r = make_float4(fmaf(beta, dx, q.x), fmaf(beta, dy, q.y), fmaf(beta, dz, q.z), fmaf(beta, dw, q.w));
+    dx = fmaf(g.x, s.x, -q.x);
+    dy = fmaf(g.y, s.y, -q.y);
+    dz = fmaf(g.z, s.z, -q.z);
+    dw = fmaf(g.w, s.w, -q.w);
   }
+  q = make_float4(q.x + dx, q.y + dy, q.z + dz, q.w + dw);
+  r = make_float4(fmaf(beta, dx, q.x), fmaf(beta, dy, q.y), fmaf(beta, dz, q.z), fmaf(beta, dw, q.w));
 }
 
 // w = b - lambda * L^T(r) at one pixel, per channel

@@ -159,6 +159,13 @@ __device__ __forceinline__ float lane_from_right(float v) {  // lane i <- lane i
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
+// Bits [max(a, 0), min(b, n)) set: the rows i of a wave with a <= i < b.
+__device__ __forceinline__ unsigned row_bits(int a, int b, int n) {
+  a = min(max(a, 0), n);
+  b = min(max(b, 0), n);
+  return ((1u << b) - 1u) & ~((1u << a) - 1u);
+}
+
 // BORDER = false is the fast path for tiles whose region lies at least one
 // pixel inside the image on every side: no neighbour there leaves the image, so
 // the boundary selects disappear. Rows are skipped once they fall outside the
@@ -211,15 +218,16 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
 #pragma unroll
   for (int i = 0; i < P; ++i) y[i] = zero2;
   for (int it = 0; it < J.T; ++it) {
-    const int lo = it + 1 + eu, hi = RH - (it + 1) - ed;
+    // Live rows of this wave as bit masks (uniform): y on [lo, hi], q on [lo, hi).
+    const int lo = it + 1 + eu - wave * P, hi = RH - (it + 1) - ed - wave * P;
+    const unsigned ym = row_bits(lo, hi + 1, P), qm = row_bits(lo, hi, P);
     sBot[wave * kRW + lane] = make_float2(r[P - 1].x, r[P - 1].y);
     __syncthreads();
     const float2 up_lds = sBot[(wave > 0 ? wave - 1 : 0) * kRW + lane];
     const float2 up0 = (wave > 0) ? up_lds : zero2;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      const int ry = wave * P + i;
-      if (ry >= lo && ry <= hi) {
+      if (ym & (1u << i)) {
         const int j = jb + i;
         const float lx = lane_from_left(r[i].z), ly = lane_from_left(r[i].w);
         float2 up = (i > 0) ? make_float2(r[i - 1].x, r[i - 1].y) : up0;
@@ -238,8 +246,7 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
     const float beta = sBeta[it];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      const int ry = wave * P + i;
-      if (ry >= lo && ry < hi) {
+      if (qm & (1u << i)) {
         const int j = jb + i;
         const float rx = lane_from_right(y[i].x), rv = lane_from_right(y[i].y);
         const float2 down = (i < P - 1) ? y[i + 1] : down_last;
@@ -288,7 +295,7 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
 }
 
 template <int KIND, int CONSTR, bool MASK, int NW, int P>
-__global__ __launch_bounds__(NW * 64) void fgp_col_kernel(FgpPlainArgs P_) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void fgp_col_kernel(FgpPlainArgs P_) {
   __shared__ float2 sBot[NW * kRW];
   __shared__ float2 sTop[NW * kRW];
   __shared__ float sBeta[kMaxFuse];
@@ -364,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void fgp_plain_kernel(FgpPlainArgs P) {
 // list and its workgroups stride through it.
 // ---------------------------------------------------------------------------
 template <int CONSTR, int NW, int P>
-__global__ __launch_bounds__(NW * 64) void fgp_batched_kernel(FgpBatchedArgs A) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void fgp_batched_kernel(FgpBatchedArgs A) {
   __shared__ float2 sBot[NW * kRW];
   __shared__ float2 sTop[NW * kRW];
   __shared__ float sBeta[kMaxFuse];
