@@ -40,6 +40,13 @@ def _mean(v):
     return sum(v) / len(v)
 
 
+def _largest(v):
+    """Mean over the dispatches within 10 % of the largest: the calibration
+    copies, not the small device copies the same run also makes."""
+    top = max(v)
+    return _mean([x for x in v if x >= 0.9 * top])
+
+
 def stats(csv_path, out, cmd):
     rows = list(csv.DictReader(open(csv_path)))
     lines = ["# rocprofv3 kernel statistics", "", f"Command: `{cmd}`", "",
@@ -53,8 +60,8 @@ def stats(csv_path, out, cmd):
 def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, kernel_prefix="void ctv::fgp_col_kernel"):
     fetch, write, valu = _counters(fetch_dir), _counters(write_dir), _counters(valu_dir)
     copy = next(k for k in fetch if "copyBuffer" in k)
-    f_factor = copy_bytes / 1024.0 / _mean(fetch[copy]["FETCH_SIZE"])
-    w_factor = copy_bytes / 1024.0 / _mean(write[copy]["WRITE_SIZE"])
+    f_factor = copy_bytes / 1024.0 / _largest(fetch[copy]["FETCH_SIZE"])
+    w_factor = copy_bytes / 1024.0 / _largest(write[copy]["WRITE_SIZE"])
     per_kernel = {}
     for k in sorted(fetch):
         if not k.startswith(kernel_prefix):
