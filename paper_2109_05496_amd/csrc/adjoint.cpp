@@ -1,5 +1,5 @@
 // Host side of ctv_denoise_backward: segment-wise recomputation from the
-// forward checkpoints (single-iteration launches that keep every r_k), the
+// forward checkpoints (fused launches that also store every r_k), the
 // Eq. (18) output adjoint, one reverse-step launch per iteration, and the
 // deterministic lambda-gradient reduction.
 #include <hip/hip_runtime.h>
@@ -94,12 +94,16 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
     return CTV_OK;
   }
 
+  // Recomputation runs the fused column-tile kernel (default shape), storing
+  // r after every iteration; results do not depend on the tiling.
   Tiling tl;
   ctv_params tp = *p;
-  tp.fuse = 1;
+  tp.fuse = 0;
+  tp.tile_waves = 0;
+  tp.tile_rows = 0;
+  tp.iters = c;
   st = choose_tiling(&tp, m, n, batch, &tl);
   if (st) return st;
-  tl.T = 1;
   std::vector<float> beta;
   momentum_table(p->method, K + 1, beta);
   const int tiles_x = adj_tiles_x(n), tiles_per_img = tiles_x * adj_tiles_y(m);
@@ -132,13 +136,18 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
       const int ks = sgi * c, ke = std::min(ks + c, K);
       const float* ck = (sgi == 0) ? nullptr : saved + (size_t)(sgi - 1) * (st_full / 4) + st_off;
-      // recompute: state after iteration k into slot[k - ks - 1]
+      // recompute iterations ks+1 .. kstop: slot[j] receives r_{ks+j+2} (plane 1) for
+      // every j, and the full state after each launch's last iteration
       const int kstop = (sgi == nseg - 1) ? ke : ke - 1;
       const float* prev = ck;
-      for (int k = ks; k < kstop; ++k) {
-        st = fgp_launch(p, tl, cb, m, n, a.b, support, lambda_host + c0, beta, k, 1, prev, slot(k - ks), nullptr, s);
+      for (int k = ks; k < kstop;) {
+        const int Tl = std::min(tl.T, kstop - k);
+        float* last = slot(k + Tl - 1 - ks);
+        st = fgp_launch(p, tl, cb, m, n, a.b, support, lambda_host + c0, beta, k, Tl, prev, last, nullptr, s,
+                        slot(k - ks), (long long)(st_stride / 4));
         if (st) return st;
-        prev = slot(k - ks);
+        prev = last;
+        k += Tl;
       }
       if (sgi == nseg - 1) {
         a.r = slot(ke - ks - 1);  // q_K in plane 0

@@ -129,7 +129,10 @@ size_t denoise_ws_bytes(int batch, int m, int n) {
 
 ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int n, const float* b,
                       const uint8_t* support, const float* lam, const std::vector<float>& beta, int k, int Tl,
-                      const float* src, float* dst, float* x, hipStream_t s) {
+                      const float* src, float* dst, float* x, hipStream_t s, float* r_hist,
+                      long long r_hist_stride) {
+  if (r_hist && (tl.shape.waves != 8 || tl.shape.rows_per_thread != 8))
+    return fail(CTV_ERR_INVALID_ARG, "r history needs the 8 x 8 column tile");
   FgpPlainArgs a;
   std::memset(&a, 0, sizeof(a));
   a.b = b;
@@ -144,6 +147,8 @@ ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int 
   a.st_in = src;
   a.st_out = dst;
   a.x = x;
+  a.r_hist = r_hist;
+  a.r_hist_stride = r_hist_stride;
   a.T = Tl;
   a.halo = std::max(1, Tl + (x ? 1 : 0));
   for (int i = 0; i < kMaxFuse; ++i) a.beta[i] = (i < Tl) ? beta[(size_t)(k + 1 + i)] : 0.0f;

@@ -30,8 +30,11 @@ size_t denoise_ws_bytes(int batch, int m, int n);
 // One launch of the plain fused kernel: iterations k+1 .. k+Tl on a chunk of
 // cb <= 32 images (per-image lambdas lam[0..cb)), from state src (nullptr =
 // cold start) into dst (nullptr = not stored); x != nullptr adds Eq. (18).
+// r_hist != nullptr (8 x 8 column tile only) also stores r after each fused
+// iteration i into plane 1 of the state at r_hist + i * r_hist_stride floats.
 ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int n, const float* b,
                       const uint8_t* support, const float* lam, const std::vector<float>& beta, int k, int Tl,
-                      const float* src, float* dst, float* x, hipStream_t s);
+                      const float* src, float* dst, float* x, hipStream_t s, float* r_hist = nullptr,
+                      long long r_hist_stride = 0);
 
 }  // namespace ctv

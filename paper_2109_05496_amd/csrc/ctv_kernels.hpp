@@ -23,6 +23,9 @@ struct FgpPlainArgs {
   float beta[kMaxFuse];  // beta[i] = (t_k - 1)/t_{k+1} for the i-th fused iteration k
   float lam[kPlainChunk];
   float c[kPlainChunk];  // 1 / (8 lambda)
+  float* r_hist;         // 8 x 8 column tile only: states [T][chunk][2][m][n][4] whose plane 1
+                         // receives r after each fused iteration (output pixels), or nullptr
+  long long r_hist_stride;  // floats from one iteration's state to the next
 };
 
 struct BatchImage {

@@ -36,6 +36,8 @@ struct TileJob {
   float lam, c;
   Radii R;
   int T;
+  float4* r_hist;          // r after each fused iteration (plane 1 of consecutive states), or nullptr
+  long long hist_stride;   // float4 elements from one iteration's state to the next
 };
 
 template <int KIND, int CONSTR, bool MASK, int RH>
@@ -171,7 +173,7 @@ __device__ __forceinline__ unsigned row_bits(int a, int b, int n) {
 // the boundary selects disappear. Rows are skipped once they fall outside the
 // part of the region that can still reach the output (the shrinking trapezoid
 // of the fused iterations); one row more than the q rows needs y.
-template <int KIND, int CONSTR, bool MASK, int NW, int P, bool BORDER>
+template <int KIND, int CONSTR, bool MASK, int NW, int P, bool BORDER, bool HIST = false>
 __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, const float* sBeta,
                                              float2* __restrict__ sBot, float2* __restrict__ sTop) {
   constexpr int RH = NW * P;
@@ -214,6 +216,7 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
   // up, so at iteration t the needed rows are [t + eu, RH - t - ed).
   const int ed = H - J.T;
   const int eu = ed - (J.x ? 1 : 0);
+  const bool col_out = lane >= H && lane < kRW - H && kin;
   float2 y[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) y[i] = zero2;
@@ -255,9 +258,18 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
         dual_update<KIND>(g, J.R, beta, q[i], r[i]);
       }
     }
+    if (HIST) {
+      // r_{k+1} of this iteration for the output part of the tile (the reverse pass reads it)
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int j = jb + i;
+        const int ry = wave * P + i;
+        if (col_out && ry >= H && ry < RH - H && (!BORDER || j < J.m))
+          J.r_hist[it * J.hist_stride + (long long)j * J.n + k] = r[i];
+      }
+    }
   }
 
-  const bool col_out = lane >= H && lane < kRW - H && kin;
   if (J.x) {
     sBot[wave * kRW + lane] = make_float2(q[P - 1].x, q[P - 1].y);
     __syncthreads();
@@ -294,7 +306,8 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
   }
 }
 
-template <int KIND, int CONSTR, bool MASK, int NW, int P>
+// HIST: also store r after every fused iteration (the adjoint's recomputation).
+template <int KIND, int CONSTR, bool MASK, int NW, int P, bool HIST = false>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void fgp_col_kernel(FgpPlainArgs P_) {
   __shared__ float2 sBot[NW * kRW];
   __shared__ float2 sTop[NW * kRW];
@@ -320,13 +333,15 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
   J.c = P_.c[img];
   J.R = P_.R;
   J.T = P_.T;
+  J.r_hist = HIST ? reinterpret_cast<float4*>(P_.r_hist) + img * 2 * px + px : nullptr;
+  J.hist_stride = P_.r_hist_stride / 4;
   const int H = P_.halo;
   const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (NW * P - 2 * H) - H;
   const bool interior = c0 >= 1 && c0 + kRW <= J.n - 1 && r0 >= 1 && r0 + NW * P <= J.m - 1;
   if (interior)
-    fgp_tile_col<KIND, CONSTR, MASK, NW, P, false>(J, H, sBeta, sBot, sTop);
+    fgp_tile_col<KIND, CONSTR, MASK, NW, P, false, HIST>(J, H, sBeta, sBot, sTop);
   else
-    fgp_tile_col<KIND, CONSTR, MASK, NW, P, true>(J, H, sBeta, sBot, sTop);
+    fgp_tile_col<KIND, CONSTR, MASK, NW, P, true, HIST>(J, H, sBeta, sBot, sTop);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,6 +374,8 @@ __global__ __launch_bounds__(kThreads) void fgp_plain_kernel(FgpPlainArgs P) {
   J.c = P.c[img];
   J.R = P.R;
   J.T = P.T;
+  J.r_hist = nullptr;
+  J.hist_stride = 0;
   fgp_tile<KIND, CONSTR, MASK, RH>(J, P.halo, sBeta, sA1, sA2, sY);
 }
 
@@ -403,6 +420,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
     J.c = D.c;
     J.R = D.R;
     J.T = Ti;
+    J.r_hist = nullptr;
+    J.hist_stride = 0;
     const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (NW * P - 2 * H) - H;
     const bool interior = c0 >= 1 && c0 + kRW <= J.n - 1 && r0 >= 1 && r0 + NW * P <= J.m - 1;
     const int sel = (D.kind * 2 + (J.mask ? 1 : 0)) * 2 + (interior ? 0 : 1);
@@ -549,6 +568,11 @@ static hipError_t launch_plain_kind(const FgpPlainArgs& a, int constr, bool mask
 
 template <int KIND, int CONSTR, bool MASK>
 static hipError_t launch_col_shape(const FgpPlainArgs& a, int nw, int p, int nb, hipStream_t s) {
+  if (a.r_hist) {   // the r-history variant exists for the default 8 x 8 shape only
+    if (nw != 8 || p != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fgp_col_kernel<KIND, CONSTR, MASK, 8, 8, true>), dim3(nb), dim3(8 * 64), 0, s, a);
+    return hipGetLastError();
+  }
 #define CTV_COL(NW_, P_)                                                                        \
   if (nw == NW_ && p == P_) {                                                                   \
     hipLaunchKernelGGL((fgp_col_kernel<KIND, CONSTR, MASK, NW_, P_>), dim3(nb), dim3(NW_ * 64), 0, s, a); \
