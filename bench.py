@@ -168,6 +168,63 @@ def bench_pr(ctv, synth, torch, dev, reps=2):
             "fgp_Mpx_it_s_equiv": round(fgp_px_it / ms / 1e3, 1), "fft2_per_outer_iteration": 2 * len(P["distances"]) + 2}
 
 
+def median_ms(fn, reps, torch, stream, before=None):
+    """Median milliseconds of fn() over reps, each bracketed by its own HIP
+    events; before() (untimed) runs ahead of every repetition."""
+    fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        if before is not None:
+            before()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def bench_small(ctv, synth, torch, dev, reps=20):
+    """64 x 64, type-1i, lambda 0.05, K = 100: latency of one solve."""
+    c = synth.config1(0)
+    b = torch.as_tensor(c["b"]).to(dev)
+    x = torch.empty_like(b)
+    ws = torch.empty(ctv.workspace_size(64, 64, 1, iters=c["iters"])[0], dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    ms = median_ms(lambda: ctv.denoise(b, c["lam"], kind="1i", iters=c["iters"], out=x, workspace=ws),
+                   reps, torch, stream)
+    return {"workload": "64x64 complex64, type-1i, lambda 0.05, K=100, |x|<=1", "us_per_solve": round(ms * 1e3, 1),
+            "Mpx_it_s": round(64 * 64 * c["iters"] / ms / 1e3, 1)}
+
+
+def bench_out_of_cache(ctv, synth, torch, dev, size=8192, iters=48, reps=7):
+    """The masked configuration at 8192^2 (about 5.4 GB resident: b, x, two
+    dual-state buffers, mask), type-1i: warm median, and median with a 512 MB
+    write ahead of every repetition so the 256 MB Infinity Cache holds none of
+    the working set."""
+    c = synth.config2(0, size=size)
+    b = torch.as_tensor(c["b"]).to(dev)
+    mask = torch.as_tensor(c["mask"]).to(dev)
+    x = torch.empty_like(b)
+    ws = torch.empty(ctv.workspace_size(size, size, 1, iters=iters)[0], dtype=torch.uint8, device=dev)
+    flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def run():
+        ctv.denoise(b, c["lam"], kind="1i", support=mask, iters=iters, out=x, workspace=ws)
+
+    warm = median_ms(run, reps, torch, stream)
+    cold = median_ms(run, reps, torch, stream, before=lambda: flush.fill_(1.0))
+    px_it = size * size * iters
+    return {"workload": f"masked {size}x{size} complex64, type-1i, K={iters}", "warm_ms": round(warm, 3),
+            "cold_ms": round(cold, 3), "warm_Mpx_it_s": round(px_it / warm / 1e3, 1),
+            "cold_Mpx_it_s": round(px_it / cold / 1e3, 1),
+            "cold_hbm_effective_frac": round(px_it * BYTES_PER_PX_IT_MASKED / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -258,6 +315,8 @@ def main():
            "wall_s": round(wall, 3),
            "roofline": roof}
     if not args.no_extras:
+        out["small_64"] = bench_small(ctv, synth, torch, dev)
+        out["out_of_cache_8192"] = bench_out_of_cache(ctv, synth, torch, dev)
         out["batched"] = bench_batched(ctv, synth, torch, dev)
         out["adjoint"] = bench_adjoint(ctv, synth, torch, dev)
         out["phase_retrieval"] = bench_pr(ctv, synth, torch, dev)

@@ -20,8 +20,12 @@ namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int adj_tiles_x(int n) { return (n + (64 - 2 * adj_halo()) - 1) / (64 - 2 * adj_halo()); }
-int adj_tiles_y(int m) { return (m + (adj_tile_rows() - 2 * adj_halo()) - 1) / (adj_tile_rows() - 2 * adj_halo()); }
+// Reverse steps run up to kMaxRev per launch; every launch of a call uses the
+// halo of the longest one, so the tile grid (and the lambda-gradient slot of
+// each tile) is the same throughout.
+int adj_halo(int ckpt) { return std::min(kMaxRev, std::max(ckpt, 1)) + 1; }
+int adj_tiles_x(int n, int h) { return (n + (64 - 2 * h) - 1) / (64 - 2 * h); }
+int adj_tiles_y(int m, int h) { return (m + (adj_tile_rows() - 2 * h) - 1) / (adj_tile_rows() - 2 * h); }
 
 struct BwdLayout {
   size_t seg, adj, lam, total;
@@ -30,9 +34,10 @@ struct BwdLayout {
 BwdLayout layout(int batch, int m, int n, int ckpt) {
   BwdLayout L;
   const size_t st = align_up(state_bytes(batch, m, n));
+  const int h = adj_halo(ckpt);
   L.seg = (size_t)std::max(ckpt, 1) * st;
   L.adj = 2 * st;
-  L.lam = align_up((size_t)batch * adj_tiles_x(n) * adj_tiles_y(m) * sizeof(double));
+  L.lam = align_up((size_t)batch * adj_tiles_x(n, h) * adj_tiles_y(m, h) * sizeof(double));
   L.total = L.seg + L.adj + L.lam;
   return L;
 }
@@ -106,7 +111,8 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
   if (st) return st;
   std::vector<float> beta;
   momentum_table(p->method, K + 1, beta);
-  const int tiles_x = adj_tiles_x(n), tiles_per_img = tiles_x * adj_tiles_y(m);
+  const int halo = adj_halo(c);
+  const int tiles_x = adj_tiles_x(n, halo), tiles_per_img = tiles_x * adj_tiles_y(m, halo);
 
   for (int c0 = 0; c0 < batch; c0 += kPlainChunk) {
     const int cb = std::min(kPlainChunk, batch - c0);
@@ -123,6 +129,7 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
     a.n = n;
     a.tiles_x = tiles_x;
     a.tiles_per_img = tiles_per_img;
+    a.halo = halo;
     a.R = make_radii(p->tv_kind, p->alpha);
     for (int i = 0; i < cb; ++i) {
       const double lam = lambda_host[c0 + i];
@@ -150,20 +157,30 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
         k += Tl;
       }
       if (sgi == nseg - 1) {
-        a.r = slot(ke - ks - 1);  // q_K in plane 0
+        for (int i = 0; i < kMaxRev; ++i) a.r[i] = nullptr;
+        a.r[0] = slot(ke - ks - 1);  // q_K in plane 0
+        a.steps = 0;
         a.adj_in = nullptr;
         a.adj_out = cur;
         hipError_t e = launch_adj_output(a, p->constraint, cb, s);
         if (e != hipSuccess) return hip_fail(e, "adjoint output step");
       }
-      for (int k = ke; k >= ks + 1; --k) {
-        a.r = (k == ks + 1) ? ck : slot(k - ks - 2);
+      // reverse steps ke, ke-1, ..., ks+1, up to kMaxRev per launch; r_k is in
+      // plane 1 of slot[k - ks - 2], r_{ks+1} in the checkpoint (zero for k = 1)
+      for (int khi = ke; khi >= ks + 1;) {
+        const int steps = std::min(kMaxRev, khi - ks);
+        for (int i = 0; i < kMaxRev; ++i) {
+          const int k = khi - i;
+          a.r[i] = (i >= steps) ? nullptr : (k == ks + 1) ? ck : slot(k - ks - 2);
+          a.beta[i] = (i < steps && k >= 2) ? beta[(size_t)(k - 1)] : 0.0f;
+        }
+        a.steps = steps;
         a.adj_in = cur;
-        a.adj_out = (k == 1) ? nullptr : nxt;
-        a.beta = (k >= 2) ? beta[(size_t)(k - 1)] : 0.0f;
+        a.adj_out = (khi - steps + 1 == 1) ? nullptr : nxt;
         hipError_t e = launch_adj_step(a, p->tv_kind, p->constraint, cb, s);
         if (e != hipSuccess) return hip_fail(e, "adjoint step");
         std::swap(cur, nxt);
+        khi -= steps;
       }
     }
     hipError_t e = launch_lam_final(a.lam_acc, tiles_per_img, cb, grad_lambda + c0, s);

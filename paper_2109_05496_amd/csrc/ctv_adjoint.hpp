@@ -8,26 +8,29 @@
 
 namespace ctv {
 
+constexpr int kMaxRev = 4;  // reverse steps fused per launch
+
 struct AdjStepArgs {
-  const float* b;         // chunk base, complex64
-  const uint8_t* mask;    // [m][n] or nullptr
-  const float* r;         // dual state whose plane 1 is r_k (reverse step; nullptr = zero)
-                          // or whose plane 0 is q_K (output step)
-  const float* adj_in;    // adjoint state [2][m][n][4]: (A, B)
-  float* adj_out;         // same layout, nullptr on the last reverse step
-  float* grad_b;          // complex64, read-modify-write
-  const float* grad_x;    // complex64 incoming gradient (output step)
-  double* lam_acc;        // [chunk][tiles_per_img]
+  const float* b;           // chunk base, complex64
+  const uint8_t* mask;      // [m][n] or nullptr
+  const float* r[kMaxRev];  // reverse step: per fused step, the dual state whose plane 1 is r_k
+                            // (nullptr = zero); output step: r[0] is the state whose plane 0 is q_K
+  const float* adj_in;      // adjoint state [2][m][n][4]: (A, B)
+  float* adj_out;           // same layout, nullptr after the last reverse step
+  float* grad_b;            // complex64, read-modify-write
+  const float* grad_x;      // complex64 incoming gradient (output step)
+  double* lam_acc;          // [chunk][tiles_per_img]
   int m, n, tiles_x, tiles_per_img;
-  float beta;             // beta_{k-1}
+  int halo;                 // tile halo, >= steps + 1, the same for every launch of a call
+  int steps;                // reverse steps in this launch, 1..kMaxRev
+  float beta[kMaxRev];      // beta_{k-1} of each fused step k
   Radii R;
   float lam[kPlainChunk];
-  float c[kPlainChunk];   // 1/(8 lambda)
-  float cc[kPlainChunk];  // 1/(8 lambda^2) (0 for lambda = 0)
+  float c[kPlainChunk];     // 1/(8 lambda)
+  float cc[kPlainChunk];    // 1/(8 lambda^2) (0 for lambda = 0)
 };
 
 int adj_tile_rows();
-int adj_halo();
 hipError_t launch_adj_step(const AdjStepArgs& a, int kind, int constr, int batch, hipStream_t s);
 hipError_t launch_adj_output(const AdjStepArgs& a, int constr, int batch, hipStream_t s);
 hipError_t launch_pc_vjp(const float* b, const uint8_t* mask, const float* xbar, float* gb, long long px, int batch,

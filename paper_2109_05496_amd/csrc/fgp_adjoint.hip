@@ -19,9 +19,10 @@
 // their adjoints are zero here.
 //
 // Tiles: column-register layout as in the forward kernel (lane = column,
-// wave = P consecutive rows, DPP for left/right, LDS for wave-boundary rows),
-// one reverse step per launch, halo 2 (the four stencil stages read up/left,
-// down/right, up/left, down/right).
+// wave = P consecutive rows, DPP for left/right, LDS for wave-boundary rows).
+// Up to kMaxRev reverse steps run per launch; the four stencil stages of a step
+// read up/left, down/right, up/left, down/right, which widens the dependence of
+// (A, B) by one pixel per step, so a launch of s steps needs a halo of s + 1.
 #include <hip/hip_runtime.h>
 
 #include "ctv_adjoint.hpp"
@@ -32,7 +33,6 @@ namespace ctv {
 namespace {
 
 constexpr int kRW = 64;
-constexpr int kHalo = 2;
 
 __device__ __forceinline__ float from_left(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
@@ -117,14 +117,18 @@ __device__ __forceinline__ float4 proj_s_vjp(float4 g, float4 a, const Radii& R)
 struct AdjJob {
   const float2* b;
   const uint8_t* mask;
-  const float4* r;      // r_k plane (nullptr = zero, i.e. r_1 = q_0 = 0)
-  const float4* adj_in; // [2][m][n]: A then B
-  float4* adj_out;      // [2][m][n] or nullptr (last reverse step)
-  float2* gb;           // grad_b, read-modify-write
-  double* lam_acc;      // per-tile accumulator slot
+  // r_k plane of each fused step (nullptr = zero, i.e. r_1 = q_0 = 0); the
+  // output step reads q_K through r0. Separate members, not an array, so that
+  // picking one with the runtime step index stays in scalar registers.
+  const float4 *r0, *r1, *r2, *r3;
+  const float4* adj_in;      // [2][m][n]: A then B
+  float4* adj_out;           // [2][m][n] or nullptr (after the last reverse step)
+  float2* gb;                // grad_b, read-modify-write
+  double* lam_acc;           // per-tile accumulator slot
   int m, n, tx, ty;
-  float lam, c, cc;     // lambda, 1/(8 lambda), 1/(8 lambda^2)
-  float beta;           // beta_{k-1}
+  int steps;                 // reverse steps fused in this launch
+  float lam, c, cc;          // lambda, 1/(8 lambda), 1/(8 lambda^2)
+  float beta0, beta1, beta2, beta3;  // beta_{k-1} of each fused step
   Radii R;
 };
 
@@ -140,11 +144,16 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
   return s;
 }
 
+// J.steps reverse steps k, k-1, ... on one tile with halo H >= steps + 1: a step
+// reads (A, B) one pixel and r_k two pixels around each point it updates, so
+// the valid part of the tile shrinks by one pixel per side and step. (A, B) and
+// the running bbar (started from grad_b, so the sum is taken in the same order
+// as one step per launch) stay in registers between steps and are stored once,
+// for the tile's output pixels.
 template <int KIND, int CONSTR, bool MASK, int NW, int P, bool BORDER>
-__device__ __forceinline__ void adj_tile(const AdjJob& J, float2* sX1, float2* sX2, float2* sX3, float2* sX4,
-                                         double* red) {
+__device__ __forceinline__ void adj_tile(const AdjJob& J, const int H, float2* sX1, float2* sX2, float2* sX3,
+                                         float2* sX4, double* red) {
   constexpr int RH = NW * P;
-  constexpr int H = kHalo;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (RH - 2 * H) - H;
@@ -157,129 +166,145 @@ __device__ __forceinline__ void adj_tile(const AdjJob& J, float2* sX1, float2* s
   const float2 z2 = make_float2(0.0f, 0.0f);
   const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
-  float4 r[P];
-  float2 b[P];
-  bool inside[P], in[P];
+  float4 A[P], B[P];
+  float2 b[P], bacc[P];
+  bool inside[P], in[P], out[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int j = jb + i;
+    const int ry = wave * P + i;
     in[i] = kin && (!BORDER || (j >= 0 && j < J.m));
-    r[i] = z4;
+    out[i] = in[i] && ry >= H && ry < RH - H && lane >= H && lane < kRW - H;
+    A[i] = z4;
+    B[i] = z4;
     b[i] = z2;
+    bacc[i] = z2;
     inside[i] = !BORDER;
     if (in[i]) {
       const long long p = (long long)j * J.n + k;
       b[i] = J.b[p];
-      if (J.r) r[i] = J.r[p];
+      A[i] = J.adj_in[p];
+      B[i] = J.adj_in[plane + p];
       inside[i] = MASK ? (J.mask[p] != 0) : true;
+      if (out[i]) bacc[i] = J.gb[p];
     }
   }
-
-  // stage 1: w, y from r (up / left)
-  sX1[wave * kRW + lane] = make_float2(r[P - 1].x, r[P - 1].y);
-  __syncthreads();
-  float2 w[P], y[P], dd[P];
-  float s[P];
-  {
-    const float2 up_l = sX1[(wave > 0 ? wave - 1 : 0) * kRW + lane];
-    const float2 up0 = (wave > 0) ? up_l : z2;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int j = jb + i;
-      const float lx = from_left(r[i].z), ly = from_left(r[i].w);
-      float2 up = (i > 0) ? make_float2(r[i - 1].x, r[i - 1].y) : up0;
-      float2 left = make_float2(lx, ly);
-      if (BORDER) {
-        up = (j > 0) ? up : z2;
-        left = has_left ? left : z2;
-      }
-      dd[i] = make_float2((r[i].x - up.x) + (r[i].z - left.x), (r[i].y - up.y) + (r[i].w - left.y));
-      w[i] = dual_to_primal(b[i], r[i], up, left, J.lam);
-      y[i] = proj_c_s<CONSTR>(w[i], inside[i], s[i]);
-    }
-  }
-  // stage 2: g from y (down / right); gbar = J_PS^T A
-  sX2[wave * kRW + lane] = y[0];
-  __syncthreads();
-  float4 gbar[P];
-  float lterm[P];
-  {
-    const float2 dn_l = sX2[(wave < NW - 1 ? wave + 1 : wave) * kRW + lane];
-    const float2 down_last = (wave < NW - 1) ? dn_l : y[P - 1];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int j = jb + i;
-      const bool has_down = !BORDER || j < J.m - 1;
-      const float rx = from_right(y[i].x), ry = from_right(y[i].y);
-      const float2 down = (i < P - 1) ? y[i + 1] : down_last;
-      const float4 g = dual_step(r[i], y[i], down, make_float2(rx, ry), J.c, has_down, has_right);
-      float4 a = z4;
-      if (in[i]) a = J.adj_in[(long long)(jb + i) * J.n + k];
-      float4 gb = proj_s_vjp<KIND>(g, a, J.R);
-      if (BORDER) {
-        if (!has_down) gb.x = gb.y = 0.0f;
-        if (!has_right) gb.z = gb.w = 0.0f;
-      }
-      gbar[i] = gb;
-      const float l1x = has_down ? y[i].x - down.x : 0.0f, l1y = has_down ? y[i].y - down.y : 0.0f;
-      const float l2x = has_right ? y[i].x - rx : 0.0f, l2y = has_right ? y[i].y - ry : 0.0f;
-      lterm[i] = gb.x * l1x + gb.y * l1y + gb.z * l2x + gb.w * l2y;
-    }
-  }
-  // stage 3: ybar = c L^T(gbar) (up / left); wbar = J_PC^T ybar
-  sX3[wave * kRW + lane] = make_float2(gbar[P - 1].x, gbar[P - 1].y);
-  __syncthreads();
-  float2 wbar[P];
   double lam_part = 0.0;
-  {
-    const float2 up_l = sX3[(wave > 0 ? wave - 1 : 0) * kRW + lane];
-    const float2 up0 = (wave > 0) ? up_l : z2;
+
+  for (int st = 0; st < J.steps; ++st) {
+    const float4* __restrict__ rk = st == 0 ? J.r0 : st == 1 ? J.r1 : st == 2 ? J.r2 : J.r3;
+    float4 r[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      const int j = jb + i;
-      const float lx = from_left(gbar[i].z), ly = from_left(gbar[i].w);
-      float2 up = (i > 0) ? make_float2(gbar[i - 1].x, gbar[i - 1].y) : up0;
-      float2 left = make_float2(lx, ly);
-      if (BORDER) {
-        up = (j > 0) ? up : z2;
-        left = has_left ? left : z2;
+      r[i] = z4;
+      if (rk && in[i]) r[i] = rk[(long long)(jb + i) * J.n + k];
+    }
+    // stage 1: w, y from r (up / left)
+    sX1[wave * kRW + lane] = make_float2(r[P - 1].x, r[P - 1].y);
+    __syncthreads();
+    float2 w[P], y[P], dd[P];
+    float s[P];
+    {
+      const float2 up_l = sX1[(wave > 0 ? wave - 1 : 0) * kRW + lane];
+      const float2 up0 = (wave > 0) ? up_l : z2;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int j = jb + i;
+        const float lx = from_left(r[i].z), ly = from_left(r[i].w);
+        float2 up = (i > 0) ? make_float2(r[i - 1].x, r[i - 1].y) : up0;
+        float2 left = make_float2(lx, ly);
+        if (BORDER) {
+          up = (j > 0) ? up : z2;
+          left = has_left ? left : z2;
+        }
+        dd[i] = make_float2((r[i].x - up.x) + (r[i].z - left.x), (r[i].y - up.y) + (r[i].w - left.y));
+        w[i] = dual_to_primal(b[i], r[i], up, left, J.lam);
+        y[i] = proj_c_s<CONSTR>(w[i], inside[i], s[i]);
       }
-      const float2 yb = make_float2(J.c * ((gbar[i].x - up.x) + (gbar[i].z - left.x)),
-                                    J.c * ((gbar[i].y - up.y) + (gbar[i].w - left.y)));
-      wbar[i] = proj_c_vjp<CONSTR>(w[i], s[i], inside[i], yb);
-      const int ry = wave * P + i;
-      if (ry >= H && ry < RH - H && lane >= H && lane < kRW - H && in[i])
-        lam_part += (double)(-J.cc * lterm[i] - (wbar[i].x * dd[i].x + wbar[i].y * dd[i].y));
+    }
+    // stage 2: g from y (down / right); gbar = J_PS^T A
+    sX2[wave * kRW + lane] = y[0];
+    __syncthreads();
+    float4 gbar[P];
+    {
+      const float2 dn_l = sX2[(wave < NW - 1 ? wave + 1 : wave) * kRW + lane];
+      const float2 down_last = (wave < NW - 1) ? dn_l : y[P - 1];
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int j = jb + i;
+        const bool has_down = !BORDER || j < J.m - 1;
+        const float rx = from_right(y[i].x), ry = from_right(y[i].y);
+        const float2 down = (i < P - 1) ? y[i + 1] : down_last;
+        const float4 g = dual_step(r[i], y[i], down, make_float2(rx, ry), J.c, has_down, has_right);
+        float4 gb = proj_s_vjp<KIND>(g, A[i], J.R);
+        if (BORDER) {
+          if (!has_down) gb.x = gb.y = 0.0f;
+          if (!has_right) gb.z = gb.w = 0.0f;
+        }
+        gbar[i] = gb;
+        if (out[i]) {
+          const float l1x = has_down ? y[i].x - down.x : 0.0f, l1y = has_down ? y[i].y - down.y : 0.0f;
+          const float l2x = has_right ? y[i].x - rx : 0.0f, l2y = has_right ? y[i].y - ry : 0.0f;
+          lam_part += (double)(-J.cc * (gb.x * l1x + gb.y * l1y + gb.z * l2x + gb.w * l2y));
+        }
+      }
+    }
+    // stage 3: ybar = c L^T(gbar) (up / left); wbar = J_PC^T ybar
+    sX3[wave * kRW + lane] = make_float2(gbar[P - 1].x, gbar[P - 1].y);
+    __syncthreads();
+    float2 wbar[P];
+    {
+      const float2 up_l = sX3[(wave > 0 ? wave - 1 : 0) * kRW + lane];
+      const float2 up0 = (wave > 0) ? up_l : z2;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int j = jb + i;
+        const float lx = from_left(gbar[i].z), ly = from_left(gbar[i].w);
+        float2 up = (i > 0) ? make_float2(gbar[i - 1].x, gbar[i - 1].y) : up0;
+        float2 left = make_float2(lx, ly);
+        if (BORDER) {
+          up = (j > 0) ? up : z2;
+          left = has_left ? left : z2;
+        }
+        const float2 yb = make_float2(J.c * ((gbar[i].x - up.x) + (gbar[i].z - left.x)),
+                                      J.c * ((gbar[i].y - up.y) + (gbar[i].w - left.y)));
+        wbar[i] = proj_c_vjp<CONSTR>(w[i], s[i], inside[i], yb);
+        bacc[i] = make_float2(bacc[i].x + wbar[i].x, bacc[i].y + wbar[i].y);
+        if (out[i]) lam_part += (double)(-(wbar[i].x * dd[i].x + wbar[i].y * dd[i].y));
+      }
+    }
+    // stage 4: rbar = gbar - lambda L(wbar) (down / right); A' = B + (1 + beta) rbar, B' = -beta rbar
+    sX4[wave * kRW + lane] = wbar[0];
+    __syncthreads();
+    {
+      const float2 dn_l = sX4[(wave < NW - 1 ? wave + 1 : wave) * kRW + lane];
+      const float2 down_last = (wave < NW - 1) ? dn_l : wbar[P - 1];
+      const float beta = st == 0 ? J.beta0 : st == 1 ? J.beta1 : st == 2 ? J.beta2 : J.beta3;
+      const float a1 = 1.0f + beta;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int j = jb + i;
+        const bool has_down = !BORDER || j < J.m - 1;
+        const float rx = from_right(wbar[i].x), rv = from_right(wbar[i].y);
+        const float2 down = (i < P - 1) ? wbar[i + 1] : down_last;
+        const float l1x = has_down ? wbar[i].x - down.x : 0.0f, l1y = has_down ? wbar[i].y - down.y : 0.0f;
+        const float l2x = has_right ? wbar[i].x - rx : 0.0f, l2y = has_right ? wbar[i].y - rv : 0.0f;
+        const float4 rb = make_float4(fmaf(-J.lam, l1x, gbar[i].x), fmaf(-J.lam, l1y, gbar[i].y),
+                                      fmaf(-J.lam, l2x, gbar[i].z), fmaf(-J.lam, l2y, gbar[i].w));
+        A[i] = make_float4(fmaf(a1, rb.x, B[i].x), fmaf(a1, rb.y, B[i].y), fmaf(a1, rb.z, B[i].z),
+                           fmaf(a1, rb.w, B[i].w));
+        B[i] = make_float4(-beta * rb.x, -beta * rb.y, -beta * rb.z, -beta * rb.w);
+      }
     }
   }
-  // stage 4: rbar = gbar - lambda L(wbar) (down / right); outputs
-  sX4[wave * kRW + lane] = wbar[0];
-  __syncthreads();
-  {
-    const float2 dn_l = sX4[(wave < NW - 1 ? wave + 1 : wave) * kRW + lane];
-    const float2 down_last = (wave < NW - 1) ? dn_l : wbar[P - 1];
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const int j = jb + i;
-      const int ry = wave * P + i;
-      const bool has_down = !BORDER || j < J.m - 1;
-      const float rx = from_right(wbar[i].x), rv = from_right(wbar[i].y);
-      const float2 down = (i < P - 1) ? wbar[i + 1] : down_last;
-      const float l1x = has_down ? wbar[i].x - down.x : 0.0f, l1y = has_down ? wbar[i].y - down.y : 0.0f;
-      const float l2x = has_right ? wbar[i].x - rx : 0.0f, l2y = has_right ? wbar[i].y - rv : 0.0f;
-      if (ry >= H && ry < RH - H && lane >= H && lane < kRW - H && in[i]) {
-        const long long p = (long long)j * J.n + k;
-        const float2 g0 = J.gb[p];
-        J.gb[p] = make_float2(g0.x + wbar[i].x, g0.y + wbar[i].y);
-        if (J.adj_out) {
-          const float4 rb = make_float4(fmaf(-J.lam, l1x, gbar[i].x), fmaf(-J.lam, l1y, gbar[i].y),
-                                        fmaf(-J.lam, l2x, gbar[i].z), fmaf(-J.lam, l2y, gbar[i].w));
-          const float4 Bv = J.adj_in[plane + p];
-          const float a1 = 1.0f + J.beta;
-          J.adj_out[p] = make_float4(fmaf(a1, rb.x, Bv.x), fmaf(a1, rb.y, Bv.y), fmaf(a1, rb.z, Bv.z),
-                                     fmaf(a1, rb.w, Bv.w));
-          J.adj_out[plane + p] = make_float4(-J.beta * rb.x, -J.beta * rb.y, -J.beta * rb.z, -J.beta * rb.w);
-        }
+  for (int i = 0; i < P; ++i) {
+    if (out[i]) {
+      const long long p = (long long)(jb + i) * J.n + k;
+      J.gb[p] = bacc[i];
+      if (J.adj_out) {
+        J.adj_out[p] = A[i];
+        J.adj_out[plane + p] = B[i];
       }
     }
   }
@@ -290,10 +315,9 @@ __device__ __forceinline__ void adj_tile(const AdjJob& J, float2* sX1, float2* s
 // Output step: w = b - lambda L^T q_K, wbar = J_PC(w)^T xbar, bbar = wbar,
 // A = qbar_K = -lambda L(wbar), B = 0, lambdabar = -<wbar, L^T q_K>.
 template <int CONSTR, bool MASK, int NW, int P, bool BORDER>
-__device__ __forceinline__ void adj_out_tile(const AdjJob& J, const float2* __restrict__ xbar, float2* sX1,
-                                             float2* sX2, double* red) {
+__device__ __forceinline__ void adj_out_tile(const AdjJob& J, const int H, const float2* __restrict__ xbar,
+                                             float2* sX1, float2* sX2, double* red) {
   constexpr int RH = NW * P;
-  constexpr int H = kHalo;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (RH - 2 * H) - H;
@@ -319,7 +343,7 @@ __device__ __forceinline__ void adj_out_tile(const AdjJob& J, const float2* __re
     if (in[i]) {
       const long long p = (long long)j * J.n + k;
       b[i] = J.b[p];
-      q[i] = J.r[p];  // q_K plane
+      q[i] = J.r0[p];  // q_K plane
       xb[i] = xbar[p];
       inside[i] = MASK ? (J.mask[p] != 0) : true;
     }
@@ -379,19 +403,13 @@ __device__ __forceinline__ void adj_out_tile(const AdjJob& J, const float2* __re
 
 constexpr int kNW = 8, kP = 4;
 
-template <int KIND, int CONSTR, bool MASK>
-__global__ __launch_bounds__(kNW * 64) void adj_step_kernel(AdjStepArgs A) {
-  __shared__ float2 sX1[kNW * kRW], sX2[kNW * kRW], sX3[kNW * kRW], sX4[kNW * kRW];
-  __shared__ double red[kNW];
+__device__ __forceinline__ void adj_job_common(const AdjStepArgs& A, int& img, AdjJob& J) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int img = tile / A.tiles_per_img;
+  img = tile / A.tiles_per_img;
   const int t = tile - img * A.tiles_per_img;
   const long long px = (long long)A.m * A.n;
-  AdjJob J;
   J.b = reinterpret_cast<const float2*>(A.b) + img * px;
   J.mask = A.mask;
-  J.r = A.r ? reinterpret_cast<const float4*>(A.r) + img * 2 * px + px : nullptr;  // plane 1 of a state
-  J.adj_in = reinterpret_cast<const float4*>(A.adj_in) + img * 2 * px;
   J.adj_out = A.adj_out ? reinterpret_cast<float4*>(A.adj_out) + img * 2 * px : nullptr;
   J.gb = reinterpret_cast<float2*>(A.grad_b) + img * px;
   J.lam_acc = A.lam_acc + tile;
@@ -402,50 +420,57 @@ __global__ __launch_bounds__(kNW * 64) void adj_step_kernel(AdjStepArgs A) {
   J.lam = A.lam[img];
   J.c = A.c[img];
   J.cc = A.cc[img];
-  J.beta = A.beta;
   J.R = A.R;
-  const int H = kHalo;
+  J.steps = A.steps;
+}
+
+template <int KIND, int CONSTR, bool MASK>
+__global__ __launch_bounds__(kNW * 64) void adj_step_kernel(AdjStepArgs A) {
+  __shared__ float2 sX1[kNW * kRW], sX2[kNW * kRW], sX3[kNW * kRW], sX4[kNW * kRW];
+  __shared__ double red[kNW];
+  int img;
+  AdjJob J;
+  adj_job_common(A, img, J);
+  const long long px = (long long)A.m * A.n;
+  // plane 1 (r) of each step's state
+  auto rplane = [&](const float* r) { return r ? reinterpret_cast<const float4*>(r) + img * 2 * px + px : nullptr; };
+  static_assert(kMaxRev == 4, "one member per fused step");
+  J.r0 = rplane(A.r[0]);
+  J.r1 = rplane(A.r[1]);
+  J.r2 = rplane(A.r[2]);
+  J.r3 = rplane(A.r[3]);
+  J.beta0 = A.beta[0];
+  J.beta1 = A.beta[1];
+  J.beta2 = A.beta[2];
+  J.beta3 = A.beta[3];
+  J.adj_in = reinterpret_cast<const float4*>(A.adj_in) + img * 2 * px;
+  const int H = A.halo;
   const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (kNW * kP - 2 * H) - H;
   const bool interior = c0 >= 1 && c0 + kRW <= J.n - 1 && r0 >= 1 && r0 + kNW * kP <= J.m - 1;
   if (interior)
-    adj_tile<KIND, CONSTR, MASK, kNW, kP, false>(J, sX1, sX2, sX3, sX4, red);
+    adj_tile<KIND, CONSTR, MASK, kNW, kP, false>(J, H, sX1, sX2, sX3, sX4, red);
   else
-    adj_tile<KIND, CONSTR, MASK, kNW, kP, true>(J, sX1, sX2, sX3, sX4, red);
+    adj_tile<KIND, CONSTR, MASK, kNW, kP, true>(J, H, sX1, sX2, sX3, sX4, red);
 }
 
 template <int CONSTR, bool MASK>
 __global__ __launch_bounds__(kNW * 64) void adj_output_kernel(AdjStepArgs A) {
   __shared__ float2 sX1[kNW * kRW], sX2[kNW * kRW];
   __shared__ double red[kNW];
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int img = tile / A.tiles_per_img;
-  const int t = tile - img * A.tiles_per_img;
-  const long long px = (long long)A.m * A.n;
+  int img;
   AdjJob J;
-  J.b = reinterpret_cast<const float2*>(A.b) + img * px;
-  J.mask = A.mask;
-  J.r = reinterpret_cast<const float4*>(A.r) + img * 2 * px;  // plane 0 (q_K) of the final state
+  adj_job_common(A, img, J);
+  const long long px = (long long)A.m * A.n;
+  J.r0 = reinterpret_cast<const float4*>(A.r[0]) + img * 2 * px;  // plane 0 (q_K) of the final state
   J.adj_in = nullptr;
-  J.adj_out = reinterpret_cast<float4*>(A.adj_out) + img * 2 * px;
-  J.gb = reinterpret_cast<float2*>(A.grad_b) + img * px;
-  J.lam_acc = A.lam_acc + tile;
-  J.m = A.m;
-  J.n = A.n;
-  J.ty = t / A.tiles_x;
-  J.tx = t - J.ty * A.tiles_x;
-  J.lam = A.lam[img];
-  J.c = A.c[img];
-  J.cc = A.cc[img];
-  J.beta = 0.0f;
-  J.R = A.R;
   const float2* xbar = reinterpret_cast<const float2*>(A.grad_x) + img * px;
-  const int H = kHalo;
+  const int H = A.halo;
   const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (kNW * kP - 2 * H) - H;
   const bool interior = c0 >= 1 && c0 + kRW <= J.n - 1 && r0 >= 1 && r0 + kNW * kP <= J.m - 1;
   if (interior)
-    adj_out_tile<CONSTR, MASK, kNW, kP, false>(J, xbar, sX1, sX2, red);
+    adj_out_tile<CONSTR, MASK, kNW, kP, false>(J, H, xbar, sX1, sX2, red);
   else
-    adj_out_tile<CONSTR, MASK, kNW, kP, true>(J, xbar, sX1, sX2, red);
+    adj_out_tile<CONSTR, MASK, kNW, kP, true>(J, H, xbar, sX1, sX2, red);
 }
 
 // lambda = 0 or K = 0: x = P_C(b), so bbar = J_PC(b)^T xbar.
@@ -473,7 +498,6 @@ __global__ void lam_final_kernel(const double* __restrict__ acc, int tiles_per_i
 }  // namespace
 
 int adj_tile_rows() { return kNW * kP; }
-int adj_halo() { return kHalo; }
 
 hipError_t launch_adj_step(const AdjStepArgs& a, int kind, int constr, int batch, hipStream_t s) {
   const int nb = a.tiles_per_img * batch;

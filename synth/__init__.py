@@ -34,22 +34,31 @@ def piecewise_complex(H, W, n_shapes, rng, amp=(0.2, 1.0), phase=(-math.pi, math
     a0 = rng.uniform(*amp)
     p0 = rng.uniform(*phase)
     img = np.full((H, W), a0 * np.exp(1j * p0), dtype=np.complex128)
-    jj = np.arange(H)[:, None]
-    kk = np.arange(W)[None, :]
+
+    def box(c, half, size):
+        # index range holding every pixel within `half` of c, one pixel of margin
+        return max(0, int(math.floor(c - half)) - 1), min(size, int(math.ceil(c + half)) + 2)
+
     for _ in range(n_shapes):
         is_disk = rng.uniform() < 0.5
         cj = rng.uniform(0, H)
         ck = rng.uniform(0, W)
         if is_disk:
             rad = rng.uniform(0.03, 0.2) * min(H, W)
+            (j0, j1), (k0, k1) = box(cj, rad, H), box(ck, rad, W)
+            jj = np.arange(j0, j1)[:, None]
+            kk = np.arange(k0, k1)[None, :]
             sel = (jj - cj) ** 2 + (kk - ck) ** 2 <= rad * rad
         else:
             hh = rng.uniform(0.03, 0.2) * H
             hw = rng.uniform(0.03, 0.2) * W
+            (j0, j1), (k0, k1) = box(cj, hh, H), box(ck, hw, W)
+            jj = np.arange(j0, j1)[:, None]
+            kk = np.arange(k0, k1)[None, :]
             sel = (np.abs(jj - cj) <= hh) & (np.abs(kk - ck) <= hw)
         a = rng.uniform(*amp)
         p = rng.uniform(*phase)
-        img[sel] = a * np.exp(1j * p)
+        img[j0:j1, k0:k1][sel] = a * np.exp(1j * p)
     return img
 
 
