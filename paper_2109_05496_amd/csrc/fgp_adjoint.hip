@@ -118,9 +118,9 @@ struct AdjJob {
   const float2* b;
   const uint8_t* mask;
   // r_k plane of each fused step (nullptr = zero, i.e. r_1 = q_0 = 0); the
-  // output step reads q_K through r0. Separate members, not an array, so that
-  // picking one with the runtime step index stays in scalar registers.
-  const float4 *r0, *r1, *r2, *r3;
+  // output step reads q_K through r[0]. The step loop is unrolled, so both
+  // arrays are indexed with constants and stay in scalar registers.
+  const float4* r[kMaxRev];
   const float4* adj_in;      // [2][m][n]: A then B
   float4* adj_out;           // [2][m][n] or nullptr (after the last reverse step)
   float2* gb;                // grad_b, read-modify-write
@@ -128,7 +128,7 @@ struct AdjJob {
   int m, n, tx, ty;
   int steps;                 // reverse steps fused in this launch
   float lam, c, cc;          // lambda, 1/(8 lambda), 1/(8 lambda^2)
-  float beta0, beta1, beta2, beta3;  // beta_{k-1} of each fused step
+  float beta[kMaxRev];       // beta_{k-1} of each fused step
   Radii R;
 };
 
@@ -191,8 +191,10 @@ __device__ __forceinline__ void adj_tile(const AdjJob& J, const int H, float2* s
   }
   double lam_part = 0.0;
 
-  for (int st = 0; st < J.steps; ++st) {
-    const float4* __restrict__ rk = st == 0 ? J.r0 : st == 1 ? J.r1 : st == 2 ? J.r2 : J.r3;
+#pragma unroll
+  for (int st = 0; st < kMaxRev; ++st) {
+    if (st >= J.steps) break;
+    const float4* __restrict__ rk = J.r[st];
     float4 r[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
@@ -279,7 +281,7 @@ __device__ __forceinline__ void adj_tile(const AdjJob& J, const int H, float2* s
     {
       const float2 dn_l = sX4[(wave < NW - 1 ? wave + 1 : wave) * kRW + lane];
       const float2 down_last = (wave < NW - 1) ? dn_l : wbar[P - 1];
-      const float beta = st == 0 ? J.beta0 : st == 1 ? J.beta1 : st == 2 ? J.beta2 : J.beta3;
+      const float beta = J.beta[st];
       const float a1 = 1.0f + beta;
 #pragma unroll
       for (int i = 0; i < P; ++i) {
@@ -343,7 +345,7 @@ __device__ __forceinline__ void adj_out_tile(const AdjJob& J, const int H, const
     if (in[i]) {
       const long long p = (long long)j * J.n + k;
       b[i] = J.b[p];
-      q[i] = J.r0[p];  // q_K plane
+      q[i] = J.r[0][p];  // q_K plane
       xb[i] = xbar[p];
       inside[i] = MASK ? (J.mask[p] != 0) : true;
     }
@@ -434,15 +436,11 @@ __global__ __launch_bounds__(kNW * 64) void adj_step_kernel(AdjStepArgs A) {
   const long long px = (long long)A.m * A.n;
   // plane 1 (r) of each step's state
   auto rplane = [&](const float* r) { return r ? reinterpret_cast<const float4*>(r) + img * 2 * px + px : nullptr; };
-  static_assert(kMaxRev == 4, "one member per fused step");
-  J.r0 = rplane(A.r[0]);
-  J.r1 = rplane(A.r[1]);
-  J.r2 = rplane(A.r[2]);
-  J.r3 = rplane(A.r[3]);
-  J.beta0 = A.beta[0];
-  J.beta1 = A.beta[1];
-  J.beta2 = A.beta[2];
-  J.beta3 = A.beta[3];
+#pragma unroll
+  for (int st = 0; st < kMaxRev; ++st) {
+    J.r[st] = rplane(A.r[st]);
+    J.beta[st] = A.beta[st];
+  }
   J.adj_in = reinterpret_cast<const float4*>(A.adj_in) + img * 2 * px;
   const int H = A.halo;
   const int c0 = J.tx * (kRW - 2 * H) - H, r0 = J.ty * (kNW * kP - 2 * H) - H;
@@ -461,7 +459,7 @@ __global__ __launch_bounds__(kNW * 64) void adj_output_kernel(AdjStepArgs A) {
   AdjJob J;
   adj_job_common(A, img, J);
   const long long px = (long long)A.m * A.n;
-  J.r0 = reinterpret_cast<const float4*>(A.r[0]) + img * 2 * px;  // plane 0 (q_K) of the final state
+  J.r[0] = reinterpret_cast<const float4*>(A.r[0]) + img * 2 * px;  // plane 0 (q_K) of the final state
   J.adj_in = nullptr;
   const float2* xbar = reinterpret_cast<const float2*>(A.grad_x) + img * px;
   const int H = A.halo;
