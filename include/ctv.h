@@ -193,7 +193,16 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
  * Phase retrieval (Section V): FISTA (Algorithm 1) on
  *   F(x) + tau ||x||_TV + I_C(x),  F(x) = sum_d 0.5 || |A_d x| - sqrt(y_d) ||^2 (Eq. 24),
  * A_d = angular-spectrum propagation over distance d (Eq. 23), gradient Eq. (27),
- * prox = ctv FGP with lambda = tau * gamma (Eq. 15), cold dual start per prox.
+ * prox = ctv FGP with lambda = tau * gamma (Eq. 15), cold dual start per prox
+ * unless warm_start is set.
+ * Step size: fixed, or (line_search = 1) chosen by backtracking in the manner of
+ * Beck and Teboulle's FISTA, since Section III-B selects gamma by a line search
+ * without naming one: starting from the previous step, gamma is multiplied by
+ * ls_shrink until x = prox(z - gamma grad F(z)) satisfies
+ *   F(x) <= F(z) + Re<grad F(z), x - z> + ||x - z||^2 / (2 gamma),
+ * at most ls_max_trials prox evaluations per outer iteration (the last one is
+ * accepted). Each test reads four doubles back to the host, so a call with the
+ * line search synchronises `stream` once per trial.
  * m and n must be powers of two in [2, 4096].
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -208,14 +217,21 @@ typedef struct {
   ctv_params inner;              /* prox: kind, alpha, constraint, iters = K_in, fuse */
   int32_t init_backprop;         /* 1: x0 = (1/D) sum_d A_d^H sqrt(y_d); 0: x0 is read from x */
   int32_t accelerate;            /* 1: FISTA (Algorithm 1); 0: plain proximal gradient (Eq. 14) */
+  int32_t line_search;           /* 1: backtracking step (above); 0: fixed gamma */
+  float ls_shrink;               /* backtracking factor in (0, 1) (line_search = 1) */
+  int32_t ls_max_trials;         /* >= 1 prox evaluations per outer iteration (line_search = 1) */
+  int32_t warm_start;            /* 1: each prox starts from the previous prox's last dual iterate
+                                    (momentum restarted: r_1 = q_0, t_1 = 1); 0: q_0 = 0 */
 } pr_params;
 
 ctv_status pr_workspace_size(const pr_params* p, int32_t m, int32_t n, size_t* ws_bytes);
 /*   y           [D][m][n] float intensities (>= 0).
  *   x           [m][n] complex64: input x0 when init_backprop = 0; output x_K.
- *   loss_trace  [K_out] floats (device) receiving F(z_k) at each gradient point, or NULL. */
+ *   loss_trace  [K_out] floats (device) receiving F(z_k) at each gradient point, or NULL.
+ *   gamma_trace [K_out] floats (device) receiving the step used in each outer iteration, or NULL. */
 ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y, float* x,
-                        float* loss_trace, void* ws, size_t ws_bytes, ctv_stream_t stream);
+                        float* loss_trace, float* gamma_trace, void* ws, size_t ws_bytes,
+                        ctv_stream_t stream);
 
 /* Stage entry points of the phase-retrieval path (same conventions).
  * ctv_fft2: 2-D DFT of a complex64 [batch][m][n] array (m, n powers of two in

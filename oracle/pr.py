@@ -13,7 +13,15 @@ Readings where the paper is silent:
   * z / |z| at z = 0 is taken as 1 (Appendix C allows any unit phasor there);
   * with several distances, F = sum_d F_d;
   * Algorithm 1's gradient point is z_k, and x_{k-1} at k = 1 is x_0;
-  * gamma is fixed (the paper's line search is not specified).
+  * gamma is fixed by default. The paper says gamma comes from a line search
+    without naming one; ``line_search=True`` takes the backtracking rule of Beck
+    and Teboulle's FISTA: keep the previous gamma, and shrink it by ``shrink``
+    until F(x) <= F(z) + Re<grad F(z), x - z> + ||x - z||^2 / (2 gamma) holds for
+    x = prox_{gamma R}(z - gamma grad F(z)), at most ``max_trials`` prox
+    evaluations per outer iteration (the last one is accepted regardless);
+  * each prox starts its dual from q = 0 (Algorithm 2, line 1); with
+    ``warm_start=True`` it starts from the previous prox's last dual iterate,
+    with the momentum restarted (r_1 = q_0, t_1 = 1).
 
 Parity status: ``transfer``, ``A``, ``AH``, ``data_term`` and ``grad_F`` are
 pinned by closed forms and finite differences; ``fista``'s end-to-end iterates
@@ -71,13 +79,16 @@ def backprop(sqrt_y, Hs):
 
 
 def fista(y, distances, wavelength, pixel, outer, inner, tau, gamma,
-          kind="1i", alpha=0.5, constraint="modulus", x0=None, accelerate=True, inner_method="fgp"):
+          kind="1i", alpha=0.5, constraint="modulus", x0=None, accelerate=True, inner_method="fgp",
+          line_search=False, shrink=0.5, max_trials=20, warm_start=False, return_info=False):
     """Algorithm 1 with prox_{gamma R} = FGP (Algorithm 2) at lam = tau*gamma
     (inner_method="gp": the unaccelerated prox iteration of Eq. 21).
 
     y: (D, m, n) intensities. Returns (x_K, loss) where loss[k-1] = F(z_k), the
     data term at the k-th gradient point. accelerate=False gives the plain
-    proximal gradient iteration of Eq. (14) (ISTA).
+    proximal gradient iteration of Eq. (14) (ISTA). With return_info, also a
+    dict with the accepted step and the number of prox evaluations per outer
+    iteration.
     """
     y = np.asarray(y, dtype=np.float64)
     D, m, n = y.shape
@@ -86,16 +97,32 @@ def fista(y, distances, wavelength, pixel, outer, inner, tau, gamma,
     x_prev = backprop(sqrt_y, Hs) if x0 is None else np.asarray(x0, dtype=np.complex128)
     z = x_prev.copy()
     t = 1.0
-    lam = tau * gamma
-    loss = []
+    loss, steps, trials = [], [], []
+    q_warm = None
     for _ in range(outer):
-        loss.append(data_term(z, sqrt_y, Hs))
-        v = z - gamma * grad_F(z, sqrt_y, Hs)
-        x = _tv.fgp(v, lam, inner, kind, alpha, constraint, method=inner_method)
+        Fz = data_term(z, sqrt_y, Hs)
+        loss.append(Fz)
+        g = grad_F(z, sqrt_y, Hs)
+        state = None if (not warm_start or q_warm is None) else (q_warm, q_warm, 0)
+        for trial in range(max_trials if line_search else 1):
+            x, (q, _, _) = _tv.fgp(z - gamma * g, tau * gamma, inner, kind, alpha, constraint, state=state,
+                                   return_state=True, method=inner_method)
+            if not line_search or trial == max_trials - 1:
+                break
+            d = x - z
+            model = Fz + float(np.sum(g.real * d.real + g.imag * d.imag)) + float(np.sum(np.abs(d) ** 2)) / (2 * gamma)
+            if data_term(x, sqrt_y, Hs) <= model:
+                break
+            gamma *= shrink
+        steps.append(gamma)
+        trials.append(trial + 1)
+        q_warm = q
         t_new = (1.0 + np.sqrt(1.0 + 4.0 * t * t)) / 2.0
         beta = (t - 1.0) / t_new if accelerate else 0.0
         z = x + beta * (x - x_prev)
         x_prev, t = x, t_new
+    if return_info:
+        return x_prev, np.array(loss), {"gamma": np.array(steps), "trials": np.array(trials)}
     return x_prev, np.array(loss)
 
 

@@ -47,7 +47,8 @@ class PrParams(ctypes.Structure):
     _fields_ = [("struct_size", c_u32), ("num_meas", c_i32), ("distances_host", ctypes.POINTER(c_d)),
                 ("wavelength", c_d), ("pixel", c_d), ("tau", c_f), ("gamma", c_f),
                 ("outer_iters", c_i32), ("inner", Params), ("init_backprop", c_i32),
-                ("accelerate", c_i32)]
+                ("accelerate", c_i32), ("line_search", c_i32), ("ls_shrink", c_f), ("ls_max_trials", c_i32),
+                ("warm_start", c_i32)]
 
 
 _SIGS = {
@@ -67,7 +68,7 @@ _SIGS = {
     "ctv_denoise_backward": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_f),
                                      c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "pr_workspace_size": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_psz]),
-    "pr_prox_grad": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "pr_prox_grad": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "ctv_fft2_workspace_size": (c_i32, [c_i32, c_i32, c_i32, c_psz]),
     "ctv_fft2": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, c_vp, c_sz, c_vp]),
     "pr_forward": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]),

@@ -241,12 +241,14 @@ class BatchedPlan:
 
 
 def _pr_params(distances, wavelength, pixel, tau, gamma, outer, inner_iters, kind, alpha, constraint,
-               init_backprop, accelerate, fuse, inner_method="fgp"):
+               init_backprop, accelerate, fuse, inner_method="fgp", line_search=False, shrink=0.5, max_trials=20,
+               warm_start=False):
     dist = (ctypes.c_double * len(distances))(*[float(d) for d in distances])
     p = _lib.PrParams(ctypes.sizeof(_lib.PrParams), len(distances), dist, float(wavelength), float(pixel),
                       float(tau), float(gamma), int(outer), make_params(kind, alpha, constraint, inner_iters, fuse,
                                                                      method=inner_method),
-                      int(init_backprop), int(accelerate))
+                      int(init_backprop), int(accelerate), int(bool(line_search)), float(shrink), int(max_trials),
+                      int(bool(warm_start)))
     return p, dist
 
 
@@ -258,19 +260,31 @@ def _pr_ws(p, m, n, dev):
 
 def phase_retrieval(y, distances, wavelength, pixel, tau=0.01, gamma=0.0, outer=100, inner=20, kind="1i",
                     alpha=0.5, constraint="modulus", x0=None, accelerate=True, fuse=0, loss=False,
-                    inner_method="fgp"):
+                    inner_method="fgp", line_search=False, shrink=0.5, max_trials=20, warm_start=False,
+                    steps=False):
     """Algorithm 1 with the FGP prox (inner_method "gp": the Eq. 21 prox);
-    y: float32 CUDA [D, m, n] intensities."""
+    y: float32 CUDA [D, m, n] intensities. line_search: backtracking step
+    (factor `shrink`, at most `max_trials` prox evaluations per outer
+    iteration, starting from `gamma`); warm_start: each prox starts from the
+    previous one's last dual iterate. Returns x, then the data-term trace
+    (loss=True) and the step used per outer iteration (steps=True)."""
     _require_cuda(y, "y", torch.float32)
     D, m, n = y.shape
     dev = y.device
     p, _keep = _pr_params(distances, wavelength, pixel, tau, gamma, outer, inner, kind, alpha, constraint,
-                          x0 is None, accelerate, fuse, inner_method)
+                          x0 is None, accelerate, fuse, inner_method, line_search, shrink, max_trials, warm_start)
     x = torch.empty((m, n), dtype=torch.complex64, device=dev) if x0 is None else x0.clone()
     lt = torch.empty(max(outer, 1), dtype=torch.float32, device=dev) if loss else None
+    gt = torch.empty(max(outer, 1), dtype=torch.float32, device=dev) if steps else None
     ws = _pr_ws(p, m, n, dev)
-    call("pr_prox_grad", ctypes.byref(p), m, n, _ptr(y), _ptr(x), _ptr(lt), _ptr(ws), ws.numel(), _stream(dev))
-    return (x, lt[:outer]) if loss else x
+    call("pr_prox_grad", ctypes.byref(p), m, n, _ptr(y), _ptr(x), _ptr(lt), _ptr(gt), _ptr(ws), ws.numel(),
+         _stream(dev))
+    res = [x]
+    if loss:
+        res.append(lt[:outer])
+    if steps:
+        res.append(gt[:outer])
+    return res[0] if len(res) == 1 else tuple(res)
 
 
 def pr_forward(x, distances, wavelength, pixel):

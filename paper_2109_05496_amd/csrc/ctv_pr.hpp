@@ -43,5 +43,13 @@ hipError_t launch_sqrt_y(const float* y, float* sy, float2* syc, long long total
 hipError_t launch_fista(const float2* x, float2* xprev, float2* z, float beta, long long total, hipStream_t s);
 hipError_t launch_loss_final(const double* partial, int count, float* out, hipStream_t s);
 hipError_t launch_copy_c(const float2* a, float2* b, long long total, hipStream_t s);
+// Line search helpers: out[j] = sum_i partial[i * stride + j] (j < width <= 64, float64,
+// fixed order); v = z - gamma g; kLsBlocks partial pairs (Re<g, x - z>, ||x - z||^2).
+constexpr int kLsBlocks = 512;
+hipError_t launch_fill_f32(float* p, float v, long long count, hipStream_t s);
+hipError_t launch_sum_d(const double* partial, int count, int stride, int width, double* out, hipStream_t s);
+hipError_t launch_grad_step(const float2* z, const float2* g, float gamma, float2* v, long long total, hipStream_t s);
+hipError_t launch_ls_dots(const float2* g, const float2* x, const float2* z, long long total, double* partial,
+                          hipStream_t s);
 
 }  // namespace ctv

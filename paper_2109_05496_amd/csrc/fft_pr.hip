@@ -428,6 +428,60 @@ __global__ void loss_final_kernel(const double* __restrict__ partial, int count,
   *out = (float)s;
 }
 
+// out[j] = sum_i partial[i * stride + j] for j < width, in index order (deterministic).
+__global__ void sum_d_kernel(const double* __restrict__ partial, int count, int stride, int width,
+                             double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (blockIdx.x != 0 || j >= width) return;
+  double s = 0.0;
+  for (int i = 0; i < count; ++i) s += partial[(long long)i * stride + j];
+  out[j] = s;
+}
+
+__global__ __launch_bounds__(256) void fill_f32_kernel(float* __restrict__ p, float v, long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+// v = z - gamma g (the argument of Algorithm 1's prox).
+__global__ __launch_bounds__(256) void grad_step_kernel(const float2* __restrict__ z, const float2* __restrict__ g,
+                                                        float gamma, float2* __restrict__ v, long long total) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  const float2 zv = z[p], gv = g[p];
+  v[p] = make_float2(fmaf(-gamma, gv.x, zv.x), fmaf(-gamma, gv.y, zv.y));
+}
+
+// Per-block partials of Re<g, x - z> and ||x - z||^2 in float64 (the two
+// inner products of the backtracking test), [block][2].
+__global__ __launch_bounds__(256) void ls_dots_kernel(const float2* __restrict__ g, const float2* __restrict__ x,
+                                                      const float2* __restrict__ z, long long total,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[2][4];
+  double a = 0.0, q = 0.0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (long long)gridDim.x * blockDim.x) {
+    const float2 gv = g[p], xv = x[p], zv = z[p];
+    const double dx = (double)xv.x - (double)zv.x, dy = (double)xv.y - (double)zv.y;
+    a += (double)gv.x * dx + (double)gv.y * dy;
+    q += dx * dx + dy * dy;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    q += __shfl_xor(q, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    partial[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
 __global__ __launch_bounds__(256) void copy_c_kernel(const float2* __restrict__ a, float2* __restrict__ b,
                                                      long long total) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -510,6 +564,27 @@ hipError_t launch_fista(const float2* x, float2* xprev, float2* z, float beta, l
 
 hipError_t launch_loss_final(const double* partial, int count, float* out, hipStream_t s) {
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, partial, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, float v, long long count, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_d(const double* partial, int count, int stride, int width, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_d_kernel, dim3(1), dim3(64), 0, s, partial, count, stride, width, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_step(const float2* z, const float2* g, float gamma, float2* v, long long total, hipStream_t s) {
+  hipLaunchKernelGGL(grad_step_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, z, g, gamma, v, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_dots(const float2* g, const float2* x, const float2* z, long long total, double* partial,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(ls_dots_kernel, dim3(kLsBlocks), dim3(256), 0, s, g, x, z, total, partial);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ namespace {
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct PrLayout {
-  size_t tw_n, tw_m, H, sy, syc, xh, t1, t2, acc, v, xcur, xprev, z, fgp, part, total;
+  size_t tw_n, tw_m, H, sy, syc, xh, t1, t2, acc, v, xcur, xprev, z, fgp, part, g, warm, lsp, lsv, total;
 };
 
 int residual_blocks(int m, int n) { return fft_line_blocks(n, m); }
@@ -50,6 +50,10 @@ PrLayout pr_layout(int D, int m, int n) {
   L.z = take(px * 8);
   L.fgp = take(denoise_ws_bytes(1, m, n));
   L.part = take((size_t)D * residual_blocks(m, n) * 8);
+  L.g = take(px * 8);                              // grad F(z) (line search)
+  L.warm = take(2 * align_up(state_bytes(1, m, n)));  // warm-start dual: current, next
+  L.lsp = take((size_t)kLsBlocks * 2 * 8);          // inner-product partials
+  L.lsv = take(4 * 8);                              // F(z), F(x), Re<g, x - z>, ||x - z||^2
   L.total = o;
   return L;
 }
@@ -70,6 +74,10 @@ ctv_status validate_pr(const pr_params* p, int m, int n, bool need_inner) {
     if (p->outer_iters < 0) return fail(CTV_ERR_INVALID_ARG, "outer_iters must be >= 0");
     ctv_status st = validate_params(&p->inner);
     if (st) return st;
+    if (p->line_search) {
+      if (!(p->ls_shrink > 0.0f && p->ls_shrink < 1.0f)) return fail(CTV_ERR_INVALID_ARG, "ls_shrink must lie in (0, 1)");
+      if (p->ls_max_trials < 1) return fail(CTV_ERR_INVALID_ARG, "ls_max_trials must be >= 1");
+    }
   }
   return CTV_OK;
 }
@@ -219,6 +227,32 @@ ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, 
   return CTV_OK;
 }
 
+// F(x) (Eq. 24 summed over d) into *out (device double): the forward half of gradient().
+ctv_status data_term(const Ctx& c, const float2* x, double* out) {
+  float2* xh = c.at(c.L.xh);
+  float2* t1 = c.at(c.L.t1);
+  float2* t2 = c.at(c.L.t2);
+  double* part = reinterpret_cast<double*>(c.ws + c.L.part);
+  ctv_status st = fft2_to_t(c, x, xh, epilogue(kPostStore, 1.0f));
+  if (st) return st;
+  FftArgs a = line_args(xh, t1, c.at(c.L.tw_m), c.px);
+  a.in_stride = 0;
+  a.pre = kPreMulH;
+  a.H = c.Ht(0);
+  a.H_stride = c.px;
+  CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, c.D, c.s), "ifft (columns)");
+  CTV_TRY(launch_transpose(t1, t2, c.n, c.m, c.D, c.s), "transpose");
+  FftArgs r = line_args(t2, t2, c.at(c.L.tw_n), c.px);
+  r.post = kPostResidual;
+  r.scale = 1.0f / (float)((double)c.m * c.n);
+  r.sy = c.sy(0);
+  r.sy_stride = c.px;
+  r.partial = part;
+  CTV_TRY(launch_fft_lines(r, c.n, c.m, 1, c.D, c.s), "ifft (rows, residual)");
+  CTV_TRY(launch_sum_d(part, c.D * residual_blocks(c.m, c.n), 1, 1, out, c.s), "loss");
+  return CTV_OK;
+}
+
 Ctx make_ctx(const pr_params* p, int m, int n, void* ws, ctv_stream_t stream) {
   return Ctx{m, n, p->num_meas, (long long)m * n, static_cast<char*>(ws), pr_layout(p->num_meas, m, n),
              reinterpret_cast<hipStream_t>(stream)};
@@ -316,7 +350,7 @@ ctv_status pr_gradient(const pr_params* p, int32_t m, int32_t n, const float* y,
 }
 
 ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y, float* x, float* loss_trace,
-                        void* ws, size_t ws_bytes, ctv_stream_t stream) {
+                        float* gamma_trace, void* ws, size_t ws_bytes, ctv_stream_t stream) {
   ctv_status st = validate_pr(p, m, n, true);
   if (st) return st;
   if (!y || !x || !ws) return fail(CTV_ERR_INVALID_ARG, "y, x and ws must be non-NULL");
@@ -328,8 +362,11 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   float2* xprev = c.at(c.L.xprev);
   float2* z = c.at(c.L.z);
   float2* v = c.at(c.L.v);
+  float2* g = c.at(c.L.g);
   float2* acc = c.at(c.L.acc);
   float2* syc = c.at(c.L.syc);
+  double* lsv = reinterpret_cast<double*>(c.ws + c.L.lsv);
+  double* lsp = reinterpret_cast<double*>(c.ws + c.L.lsp);
   const float inv = 1.0f / (float)((double)m * n);
   if (p->init_backprop) {
     // x0 = (1/D) sum_d A_d^H sqrt(y_d): the directly back-propagated field (Section VI-A)
@@ -343,8 +380,7 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   }
   CTV_TRY(launch_copy_c(xcur, xprev, c.px, c.s), "copy");
   CTV_TRY(launch_copy_c(xcur, z, c.px, c.s), "copy");
-  const float gamma = p->gamma > 0.0f ? p->gamma : 1.0f / (float)c.D;
-  const float lam = (float)((double)p->tau * gamma);
+  float gamma = p->gamma > 0.0f ? p->gamma : 1.0f / (float)c.D;
   Tiling tl;
   st = choose_tiling(&p->inner, m, n, 1, &tl);
   if (st) return st;
@@ -355,24 +391,67 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   const size_t st_floats = state_bytes(1, m, n) / 4;
   float* fA = fws;
   float* fB = fws + ((st_floats + 63) & ~(size_t)63);
-  double t = 1.0;
-  for (int k = 0; k < p->outer_iters; ++k) {
-    // v = z_k - gamma grad F(z_k)  (Algorithm 1, line 3's argument)
-    st = gradient(c, z, v, true, gamma, loss_trace ? loss_trace + k : nullptr);
-    if (st) return st;
-    // x_k = prox_{gamma R}(v): Algorithm 2 with lambda = tau gamma, cold dual start
+  // warm start (K_in > 0 only; a prox of zero iterations is P_C(v) either way)
+  const bool warm = p->warm_start && Kin > 0;
+  float* wcur = reinterpret_cast<float*>(c.ws + c.L.warm);
+  float* wnext = wcur + align_up(state_bytes(1, m, n)) / 4;
+  bool have_warm = false;
+
+  // x_k = prox_{gamma R}(v): Algorithm 2 with lambda = tau gamma from q_0 = 0 or
+  // the warm dual; with the warm start the last launch also stores its state.
+  auto prox = [&](float lam) -> ctv_status {
     int kk = 0;
-    const float* src = nullptr;
+    const float* src = (warm && have_warm) ? wcur : nullptr;
     do {
       const int Tl = std::min(tl.T, Kin - kk);
       const bool last = (kk + Tl == Kin);
-      float* dst = last ? nullptr : (src == fA ? fB : fA);
-      st = fgp_launch(&p->inner, tl, 1, m, n, reinterpret_cast<const float*>(v), nullptr, &lam, beta, kk, Tl, src,
-                      dst, last ? reinterpret_cast<float*>(xcur) : nullptr, c.s);
-      if (st) return st;
+      float* dst = last ? (warm ? wnext : nullptr) : (src == fA ? fB : fA);
+      ctv_status e = fgp_launch(&p->inner, tl, 1, m, n, reinterpret_cast<const float*>(v), nullptr, &lam, beta, kk,
+                                Tl, src, dst, last ? reinterpret_cast<float*>(xcur) : nullptr, c.s);
+      if (e) return e;
       src = dst;
       kk += Tl;
     } while (kk < Kin);
+    return CTV_OK;
+  };
+
+  double t = 1.0;
+  for (int k = 0; k < p->outer_iters; ++k) {
+    if (!p->line_search) {
+      // v = z_k - gamma grad F(z_k)  (Algorithm 1, line 3's argument)
+      st = gradient(c, z, v, true, gamma, loss_trace ? loss_trace + k : nullptr);
+      if (st) return st;
+      st = prox((float)((double)p->tau * gamma));
+      if (st) return st;
+    } else {
+      st = gradient(c, z, g, false, 0.0f, loss_trace ? loss_trace + k : nullptr);
+      if (st) return st;
+      CTV_TRY(launch_sum_d(reinterpret_cast<const double*>(c.ws + c.L.part), c.D * residual_blocks(m, n), 1, 1,
+                           lsv, c.s), "loss");
+      for (int trial = 0;; ++trial) {
+        CTV_TRY(launch_grad_step(z, g, gamma, v, c.px, c.s), "gradient step");
+        st = prox((float)((double)p->tau * gamma));
+        if (st) return st;
+        if (trial == p->ls_max_trials - 1) break;
+        st = data_term(c, xcur, lsv + 1);
+        if (st) return st;
+        CTV_TRY(launch_ls_dots(g, xcur, z, c.px, lsp, c.s), "line search");
+        CTV_TRY(launch_sum_d(lsp, kLsBlocks, 2, 2, lsv + 2, c.s), "line search");
+        double h[4];
+        CTV_TRY(hipMemcpyAsync(h, lsv, sizeof(h), hipMemcpyDeviceToHost, c.s), "line search readback");
+        CTV_TRY(hipStreamSynchronize(c.s), "line search readback");
+        if (h[1] <= h[0] + h[2] + h[3] / (2.0 * (double)gamma)) break;
+        gamma *= p->ls_shrink;
+      }
+    }
+    if (gamma_trace) CTV_TRY(launch_fill_f32(gamma_trace + k, gamma, 1, c.s), "gamma trace");
+    if (warm) {
+      // next prox starts at (q, r) = (q_K, q_K) of this one
+      std::swap(wcur, wnext);
+      CTV_TRY(launch_copy_c(reinterpret_cast<const float2*>(wcur), reinterpret_cast<float2*>(wcur) + 2 * c.px,
+                            2 * c.px, c.s), "warm start");
+      have_warm = true;
+    }
     // t_{k+1}, z_{k+1} = x_k + ((t_k - 1)/t_{k+1}) (x_k - x_{k-1})  (lines 4-5)
     const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
     const float b = p->accelerate ? (float)((t - 1.0) / tn) : 0.0f;

@@ -102,3 +102,15 @@ def test_python_wrapper_rejects_cpu_tensors():
     import paper_2109_05496_amd as ctv
     with pytest.raises(TypeError):
         ctv.denoise(torch.zeros(4, 4, dtype=torch.complex64), 0.1)
+
+
+def test_phase_retrieval_line_search_arguments_rejected():
+    from paper_2109_05496_amd import api
+    for kw in (dict(line_search=True, shrink=1.5), dict(line_search=True, shrink=0.0),
+               dict(line_search=True, max_trials=0)):
+        p, _keep = api._pr_params((1e-3,), 532e-9, 4e-6, 0.01, 0.5, 3, 5, "1i", 0.5, "modulus", 1, 1, 0,
+                                  line_search=kw["line_search"], shrink=kw.get("shrink", 0.5),
+                                  max_trials=kw.get("max_trials", 20))
+        st = _lib.lib().pr_prox_grad(ctypes.byref(p), 8, 8, DUMMY, DUMMY, None, None, DUMMY, 1 << 40, None)
+        assert st == INVALID, kw
+        assert b"ls_" in _lib.lib().ctv_last_error()

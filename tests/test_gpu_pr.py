@@ -125,3 +125,50 @@ def test_config5_full_run():
     assert loss[-1] < 0.5 * loss[0]
     assert e1 < e0
     assert np.all(np.abs(x) <= 1 + 1e-5)
+
+
+def test_line_search_matches_oracle():
+    """Backtracking from a step that is too long: the GPU takes the same
+    accept/reject decisions as the FP64 oracle (same step trace) and the same
+    iterates to 1e-4."""
+    truth, Hs, y = small_problem(m=64, D=2, seed=7)
+    dists = P5["distances"][:2]
+    x, loss, steps = ctv().phase_retrieval(dev(y), dists, P5["wavelength"], P5["pixel"], tau=0.02, gamma=4.0,
+                                           outer=3, inner=6, kind="1i", loss=True, steps=True, line_search=True,
+                                           shrink=0.5, max_trials=8)
+    xo, lo, info = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 3, 6, 0.02, 4.0, "1i",
+                             line_search=True, shrink=0.5, max_trials=8, return_info=True)
+    assert info["trials"][0] > 1
+    np.testing.assert_array_equal(steps.cpu().numpy(), info["gamma"].astype(np.float32))
+    assert rel(x.cpu().numpy(), xo) <= 1e-4, rel(x.cpu().numpy(), xo)
+    np.testing.assert_allclose(loss.cpu().numpy(), lo, rtol=1e-4)
+
+
+def test_warm_start_matches_oracle():
+    truth, Hs, y = small_problem(m=64, D=2, seed=8)
+    dists = P5["distances"][:2]
+    kw = dict(tau=0.02, gamma=0.5, outer=3, inner=5, kind="2i")
+    x = ctv().phase_retrieval(dev(y), dists, P5["wavelength"], P5["pixel"], warm_start=True, **kw)
+    xo, _ = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 3, 5, 0.02, 0.5, "2i",
+                      warm_start=True)
+    xc, _ = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 3, 5, 0.02, 0.5, "2i")
+    assert rel(x.cpu().numpy(), xo) <= 1e-4, rel(x.cpu().numpy(), xo)
+    assert rel(xc, xo) > 1e-3          # the warm start does change the iterates
+
+
+def test_line_search_and_warm_start_config5():
+    """Full-size run (1024^2, D = 4) with both options: the step never grows, the
+    data term falls and the result stays in C."""
+    truth = synth.config5_object(seed=0)
+    fields = ctv().pr_forward(dev(truth.astype(np.complex64)), P5["distances"], P5["wavelength"], P5["pixel"])
+    inten = (fields.abs() ** 2).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    y = np.stack([synth.poisson_measure(I, P5["photons"], rng) for I in inten])
+    x, loss, steps = ctv().phase_retrieval(dev(y), P5["distances"], P5["wavelength"], P5["pixel"], tau=P5["tau"],
+                                           gamma=1.0, outer=10, inner=P5["inner"], loss=True, steps=True,
+                                           line_search=True, warm_start=True)
+    s = steps.cpu().numpy()
+    lo = loss.cpu().numpy()
+    assert np.all(np.diff(s) <= 0) and s[0] <= 1.0
+    assert lo[-1] < lo[0]
+    assert float(x.abs().max()) <= 1 + 1e-6

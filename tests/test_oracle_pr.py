@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import pr
+from oracle import pr, tv
 
 
 def naive_dft2(x, sign):
@@ -113,3 +113,52 @@ def test_fista_reduces_loss_and_phase_error(rng):
 def test_phase_rmse_ignores_global_phase(rng):
     truth = synth.config5_object(seed=1, size=16, n_shapes=3, sigma_px=1.0)
     assert pr.phase_rmse(truth * np.exp(2.2j), truth) < 1e-12
+
+
+def test_line_search_accepts_the_first_step_that_passes_the_model(rng):
+    """Backtracking: the accepted step satisfies the quadratic upper model at
+    z_1 = x_0 and the step before it (gamma / shrink) did not; steps never grow;
+    a small enough start step is accepted at once and reproduces the fixed-step
+    iteration exactly."""
+    truth, Hs, sy = small_problem(rng, m=32, D=2)
+    y = np.stack([s ** 2 for s in sy])
+    dists, wl, px = (1.0e-3, 2.0e-3), 532e-9, 4e-6
+    kw = dict(outer=5, inner=8, tau=0.002)
+    x, loss, info = pr.fista(y, dists, wl, px, gamma=8.0, line_search=True, shrink=0.5, return_info=True, **kw)
+    g_steps, trials = info["gamma"], info["trials"]
+    assert trials[0] > 1 and np.all(np.diff(g_steps) <= 0)
+    x0 = pr.backprop(sy, Hs)
+    g = pr.grad_F(x0, sy, Hs)
+    F0 = pr.data_term(x0, sy, Hs)
+
+    def passes(gam):
+        xc = tv.fgp(x0 - gam * g, 0.002 * gam, 8, "1i")
+        d = xc - x0
+        model = F0 + np.sum(g.real * d.real + g.imag * d.imag) + np.sum(np.abs(d) ** 2) / (2 * gam)
+        return pr.data_term(xc, sy, Hs) <= model
+
+    assert passes(g_steps[0]) and not passes(g_steps[0] / 0.5)
+    assert np.isclose(loss[0], F0)
+    xs, ls, info_s = pr.fista(y, dists, wl, px, gamma=g_steps[-1], line_search=True, return_info=True, **kw)
+    xf, lf = pr.fista(y, dists, wl, px, gamma=g_steps[-1], **kw)
+    if np.all(info_s["trials"] == 1):
+        np.testing.assert_array_equal(xs, xf)
+        np.testing.assert_array_equal(ls, lf)
+
+
+def test_warm_started_prox_reaches_the_same_minimiser(rng):
+    """A warm dual start changes the iterates of a short prox but not its
+    limit: with many inner iterations warm and cold starts agree; the first
+    outer iteration has no previous dual, so it is identical either way."""
+    truth, Hs, sy = small_problem(rng, m=16, D=2)
+    y = np.stack([s ** 2 for s in sy])
+    dists, wl, px = (1.0e-3, 2.0e-3), 532e-9, 4e-6
+    x1c, _ = pr.fista(y, dists, wl, px, outer=1, inner=5, tau=0.01, gamma=0.5)
+    x1w, _ = pr.fista(y, dists, wl, px, outer=1, inner=5, tau=0.01, gamma=0.5, warm_start=True)
+    np.testing.assert_array_equal(x1c, x1w)
+    xs_c, _ = pr.fista(y, dists, wl, px, outer=3, inner=4, tau=0.01, gamma=0.5)
+    xs_w, _ = pr.fista(y, dists, wl, px, outer=3, inner=4, tau=0.01, gamma=0.5, warm_start=True)
+    assert np.abs(xs_c - xs_w).max() > 1e-8
+    xl_c, _ = pr.fista(y, dists, wl, px, outer=3, inner=3000, tau=0.01, gamma=0.5)
+    xl_w, _ = pr.fista(y, dists, wl, px, outer=3, inner=3000, tau=0.01, gamma=0.5, warm_start=True)
+    np.testing.assert_allclose(xl_w, xl_c, atol=1e-6)
