@@ -68,6 +68,15 @@ typedef int32_t ctv_status;
 #define CTV_M_FGP 0
 #define CTV_M_GP 1
 
+/* Launch schedule of ctv_denoise (a tuning choice, never a change of result).
+ * CTV_S_FLOW needs ckpt_every = 0, iters > 0 and the default 8 x 8 column tile;
+ * its tiles pass the dual state through device-coherent accesses and wait (a
+ * bounded wait) for their neighbours. CTV_S_AUTO uses CTV_S_STEPS, which is
+ * faster on MI355X. */
+#define CTV_S_AUTO 0
+#define CTV_S_STEPS 1
+#define CTV_S_FLOW 2
+
 typedef void* ctv_stream_t; /* hipStream_t */
 
 typedef struct {
@@ -83,6 +92,9 @@ typedef struct {
                            LDS tile 4, 8 or 16 */
   int32_t method;       /* CTV_M_FGP: Algorithm 2 with the t_k extrapolation; CTV_M_GP: the
                            unaccelerated gradient projection of Eq. (21), r_k = q_{k-1} */
+  int32_t schedule;     /* CTV_S_AUTO, CTV_S_STEPS (one kernel launch per fused step) or
+                           CTV_S_FLOW (one persistent launch; tiles wait only on their
+                           neighbours' previous step). Results are identical. */
 } ctv_params;
 
 /* Library version (major*10000 + minor*100 + patch) and last error message. */

@@ -13,6 +13,7 @@ CTV_OK = 0
 KINDS = {"1i": 0, "1a": 1, "2i": 2, "2a": 3}
 CONSTRAINTS = {"none": 0, "modulus": 1}
 METHODS = {"fgp": 0, "gp": 1}
+SCHEDULES = {"auto": 0, "steps": 1, "flow": 2}
 
 c_f = ctypes.c_float
 c_d = ctypes.c_double
@@ -35,7 +36,7 @@ class CtvError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("struct_size", c_u32), ("tv_kind", c_i32), ("alpha", c_f),
                 ("constraint", c_i32), ("iters", c_i32), ("fuse", c_i32), ("tile_waves", c_i32),
-                ("tile_rows", c_i32), ("method", c_i32)]
+                ("tile_rows", c_i32), ("method", c_i32), ("schedule", c_i32)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -105,12 +106,15 @@ def call(name, *args):
     check(name, getattr(lib(), name)(*args))
 
 
-def make_params(kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0, tile=(0, 0), method="fgp"):
+def make_params(kind="1i", alpha=0.5, constraint="modulus", iters=100, fuse=0, tile=(0, 0), method="fgp",
+                schedule="auto"):
     if method not in METHODS:
         raise ValueError(f"unknown method {method!r}")
+    if schedule not in SCHEDULES:
+        raise ValueError(f"unknown schedule {schedule!r}")
     if kind not in KINDS:
         raise ValueError(f"unknown TV kind {kind!r}")
     if constraint not in CONSTRAINTS:
         raise ValueError(f"unknown constraint {constraint!r}")
     return Params(ctypes.sizeof(Params), KINDS[kind], float(alpha), CONSTRAINTS[constraint], int(iters),
-                  int(fuse), int(tile[0]), int(tile[1]), METHODS[method])
+                  int(fuse), int(tile[0]), int(tile[1]), METHODS[method], SCHEDULES[schedule])

@@ -59,20 +59,22 @@ def workspace_size(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", it
 
 def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, iters=100, fuse=0,
             gap=False, state=None, k0=0, return_state=False, ckpt_every=0, saved=None, out=None,
-            workspace=None, tile=(0, 0), method="fgp"):
+            workspace=None, tile=(0, 0), method="fgp", schedule="auto"):
     """K FGP iterations (Algorithm 2) + Eq. (18) on the GPU.
 
     b: complex64 CUDA tensor [m, n] or [B, m, n]. lam: float or B floats.
     support: uint8 [m, n] or None. method: "fgp" (Algorithm 2) or "gp" (the
-    unaccelerated iteration of Eq. 21). Returns x (and the duality gap as a
-    float64 tensor [B] when gap=True, and the dual state when return_state=True).
+    unaccelerated iteration of Eq. 21). schedule: "auto", "steps" (one launch
+    per fused step) or "flow" (one persistent launch); results are identical.
+    Returns x (and the duality gap as a float64 tensor [B] when gap=True, and
+    the dual state when return_state=True).
     """
     _require_cuda(b, "b", torch.complex64)
     squeeze = b.dim() == 2
     bb = b.unsqueeze(0) if squeeze else b
     B, m, n = bb.shape
     dev = bb.device
-    p = make_params(kind, alpha, constraint, iters, fuse, tile, method)
+    p = make_params(kind, alpha, constraint, iters, fuse, tile, method, schedule)
     if support is not None:
         _require_cuda(support, "support", torch.uint8)
         if tuple(support.shape) != (m, n):

@@ -37,6 +37,7 @@ ctv_status validate_params(const ctv_params* p) {
   if (p->iters < 0) return fail(CTV_ERR_INVALID_ARG, "iters must be >= 0");
   if (p->fuse < 0 || p->fuse > kMaxFuse) return fail(CTV_ERR_INVALID_ARG, "fuse must lie in [0, 16]");
   if (p->method != CTV_M_FGP && p->method != CTV_M_GP) return fail(CTV_ERR_INVALID_ARG, "unknown method");
+  if (p->schedule < CTV_S_AUTO || p->schedule > CTV_S_FLOW) return fail(CTV_ERR_INVALID_ARG, "unknown schedule");
   return CTV_OK;
 }
 
@@ -121,10 +122,14 @@ int gap_blocks_per_image(long long px) {
   return (int)std::max(1LL, std::min(256LL, b));
 }
 
+// Largest halo of the 8 x 8 tile (fuse <= 16): bounds the flow bookkeeping.
+static int flow_max_halo() { return kMaxFuse; }
+
 size_t denoise_ws_bytes(int batch, int m, int n) {
   const size_t st = align_up(state_bytes(batch, m, n));
   const size_t gap = align_up((size_t)batch * gap_blocks_per_image((long long)m * n) * sizeof(double));
-  return 2 * st + gap;
+  const size_t flow = align_up((size_t)flow_ints(std::min(batch, kPlainChunk), m, n, flow_max_halo()) * 4);
+  return 2 * st + gap + flow;
 }
 
 ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int n, const float* b,
@@ -232,9 +237,18 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
   float* bufA = reinterpret_cast<float*>(wsb);
   float* bufB = reinterpret_cast<float*>(wsb + align_up(st_full));
   double* partial = reinterpret_cast<double*>(wsb + 2 * align_up(st_full));
+  int* flow_mem = reinterpret_cast<int*>(
+      wsb + 2 * align_up(st_full) + align_up((size_t)batch * gap_blocks_per_image(px) * sizeof(double)));
   Tiling tl;
   st = choose_tiling(p, m, n, batch, &tl);
   if (st) return st;
+  const bool flow_ok = ckpt_every == 0 && p->iters > 0 && tl.shape.waves == 8 && tl.shape.rows_per_thread == 8;
+  if (p->schedule == CTV_S_FLOW && !flow_ok)
+    return fail(CTV_ERR_INVALID_ARG, "the dataflow schedule needs ckpt_every = 0, iters > 0 and the 8 x 8 tile");
+  // Automatic choice: one launch per fused step. The dataflow launch moves the
+  // dual state through device-coherent accesses, which on MI355X cost more
+  // (2048^2, K = 200: 279 vs 346 G px-it/s) than the launch tail it removes.
+  const bool use_flow = flow_ok && p->schedule == CTV_S_FLOW;
   std::vector<float> beta;
   momentum_table(p->method, k0 + p->iters + 1, beta);
   const Radii R = make_radii(p->tv_kind, p->alpha);
@@ -246,7 +260,50 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
     const float* src = state_in ? state_in + st_off : nullptr;
     int k = k0;
     const int kend = k0 + p->iters;
-    do {
+    if (use_flow) {
+      // chunks of whole fused steps, each one persistent launch
+      const int chunk_iters = (kFlowMaxIters / tl.T) * tl.T;
+      while (k < kend) {
+        const int Kc = std::min(chunk_iters, kend - k);
+        const bool final_chunk = (k + Kc == kend);
+        FgpFlowArgs fa;
+        std::memset(&fa, 0, sizeof(fa));
+        fa.b = b + 2 * img_px;
+        fa.mask = support;
+        fa.st_in = src;
+        // buf0 holds this chunk's input when it comes from the workspace
+        float* in_ws = (src == bufB + st_off) ? bufB + st_off : bufA + st_off;
+        fa.buf0 = in_ws;
+        fa.buf1 = (in_ws == bufA + st_off) ? bufB + st_off : bufA + st_off;
+        fa.m = m;
+        fa.n = n;
+        fa.batch = cb;
+        fa.halo = tl.T;
+        fa.T = tl.T;
+        fa.steps = (Kc + tl.T - 1) / tl.T;
+        fa.T_last = Kc - (fa.steps - 1) * tl.T;
+        fa.tiles_x = (n + (64 - 2 * fa.halo) - 1) / (64 - 2 * fa.halo);
+        fa.tiles_y = (m + (tl.shape.rows() - 2 * fa.halo) - 1) / (tl.shape.rows() - 2 * fa.halo);
+        float* last_state = (fa.steps % 2 == 0) ? fa.buf0 : fa.buf1;  // written by the last compute step
+        fa.st_out = (final_chunk && state_out) ? state_out + st_off : nullptr;
+        fa.x = final_chunk ? x + 2 * img_px : nullptr;
+        fa.R = R;
+        for (int i = 0; i < cb; ++i) {
+          fa.lam[i] = lambda_host[c0 + i];
+          fa.c[i] = step_of(lambda_host[c0 + i]);
+        }
+        for (int i = 0; i < Kc; ++i) fa.beta[i] = beta[(size_t)(k + 1 + i)];
+        const long long ints = flow_ints(cb, m, n, fa.halo);
+        fa.counter = flow_mem;
+        fa.err = flow_mem + 1;
+        fa.done = flow_mem + 64;
+        hipError_t e = launch_zero_f4(reinterpret_cast<float*>(flow_mem), (ints + 3) / 4, s);
+        if (e == hipSuccess) e = launch_fgp_flow(fa, p->tv_kind, p->constraint, s);
+        if (e != hipSuccess) return hip_fail(e, "fgp flow launch");
+        src = fa.st_out ? fa.st_out : last_state;
+        k += Kc;
+      }
+    } else do {
       int Tl = std::min(tl.T, kend - k);
       if (ckpt_every > 0) Tl = std::min(Tl, (k / ckpt_every + 1) * ckpt_every - k);
       const bool last = (k + Tl == kend);

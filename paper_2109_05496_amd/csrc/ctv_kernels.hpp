@@ -28,6 +28,38 @@ struct FgpPlainArgs {
   long long r_hist_stride;  // floats from one iteration's state to the next
 };
 
+// Persistent dataflow form of the plain path (8 x 8 column tile): one launch
+// runs every fused step of a chunk of images. Tasks (step, image, tile) are
+// handed out in that order from an atomic ticket; a task waits until the 3 x 3
+// neighbouring tiles of the same image have finished the previous step (the
+// halo is smaller than a tile's output, so no other tile overlaps), then runs
+// the same tile function as the per-step launches. After the compute steps one
+// more step with no iterations writes x (Eq. 18) and, if asked, the state.
+constexpr int kFlowMaxIters = 480;  // iterations per launch (the momentum table lives in kernargs)
+
+struct FgpFlowArgs {
+  const float* b;         // chunk base, complex64
+  const uint8_t* mask;    // [m][n] or nullptr
+  const float* st_in;     // initial state or nullptr (cold start)
+  float* buf0;            // ping-pong states [chunk][2][m][n][4]: step s reads buf[s % 2] (buf0 at
+  float* buf1;            // s = 0 unless st_in) and writes buf[(s + 1) % 2]
+  float* st_out;          // final state or nullptr
+  float* x;               // complex64 output
+  int* counter;           // ticket counter, zero at launch
+  int* done;              // [chunk][tiles]: steps completed, zero at launch
+  int* err;               // set to 1 if a dependency wait gave up (results then invalid)
+  int m, n, tiles_x, tiles_y, batch;
+  int halo;               // = T for every step
+  int T, T_last, steps;   // fused iterations per step (last compute step: T_last), compute steps
+  Radii R;
+  float lam[kPlainChunk];
+  float c[kPlainChunk];
+  float beta[kFlowMaxIters];  // beta[i]: momentum of the i-th iteration of this launch
+};
+hipError_t launch_fgp_flow(const FgpFlowArgs& a, int kind, int constr, hipStream_t s);
+// Ints of flow bookkeeping (counter, error flag, done flags) for `batch` images of m x n at halo h.
+long long flow_ints(int batch, int m, int n, int h);
+
 struct BatchImage {
   long long offset;          // first pixel in the packed image buffers
   long long support_offset;  // byte offset of the mask, -1 = none

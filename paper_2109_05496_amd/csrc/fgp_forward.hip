@@ -16,6 +16,8 @@
 // distance: the differences that leave the image are zero by construction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ctv_device.hpp"
 #include "ctv_kernels.hpp"
 
@@ -161,6 +163,31 @@ __device__ __forceinline__ float lane_from_right(float v) {  // lane i <- lane i
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
+// Dual-state element access. COH = true (the dataflow kernel) uses 64-bit
+// agent-scope atomic accesses, which are coherent across the XCDs' separate
+// L2 caches without any cache-wide write-back or invalidate.
+template <bool COH>
+__device__ __forceinline__ float4 ld_state(const float4* p) {
+  if (!COH) return *p;
+  unsigned long long* u = reinterpret_cast<unsigned long long*>(const_cast<float4*>(p));
+  const unsigned long long a = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long b = __hip_atomic_load(u + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_float4(__uint_as_float((unsigned)a), __uint_as_float((unsigned)(a >> 32)),
+                     __uint_as_float((unsigned)b), __uint_as_float((unsigned)(b >> 32)));
+}
+template <bool COH>
+__device__ __forceinline__ void st_state(float4* p, float4 v) {
+  if (!COH) {
+    *p = v;
+    return;
+  }
+  unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+  const unsigned long long a = (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
+  const unsigned long long b = (unsigned long long)__float_as_uint(v.z) | ((unsigned long long)__float_as_uint(v.w) << 32);
+  __hip_atomic_store(u, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(u + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Bits [max(a, 0), min(b, n)) set: the rows i of a wave with a <= i < b.
 __device__ __forceinline__ unsigned row_bits(int a, int b, int n) {
   a = min(max(a, 0), n);
@@ -173,7 +200,7 @@ __device__ __forceinline__ unsigned row_bits(int a, int b, int n) {
 // the boundary selects disappear. Rows are skipped once they fall outside the
 // part of the region that can still reach the output (the shrinking trapezoid
 // of the fused iterations); one row more than the q rows needs y.
-template <int KIND, int CONSTR, bool MASK, int NW, int P, bool BORDER, bool HIST = false>
+template <int KIND, int CONSTR, bool MASK, int NW, int P, bool BORDER, bool HIST = false, bool COH = false>
 __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, const float* sBeta,
                                              float2* __restrict__ sBot, float2* __restrict__ sTop) {
   constexpr int RH = NW * P;
@@ -204,8 +231,8 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
       const long long p = (long long)j * J.n + k;
       b[i] = J.b[p];
       if (J.st_in) {
-        q[i] = J.st_in[p];
-        r[i] = J.st_in[plane + p];
+        q[i] = ld_state<COH>(J.st_in + p);
+        r[i] = ld_state<COH>(J.st_in + plane + p);
       }
       inside[i] = MASK ? (J.mask[p] != 0) : true;
     }
@@ -299,8 +326,8 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
       const int ry = wave * P + i;
       if (col_out && ry >= H && ry < RH - H && (!BORDER || j < J.m)) {
         const long long p = (long long)j * J.n + k;
-        J.st_out[p] = q[i];
-        J.st_out[plane + p] = r[i];
+        st_state<COH>(J.st_out + p, q[i]);
+        st_state<COH>(J.st_out + plane + p, r[i]);
       }
     }
   }
@@ -342,6 +369,98 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
     fgp_tile_col<KIND, CONSTR, MASK, NW, P, false, HIST>(J, H, sBeta, sBot, sTop);
   else
     fgp_tile_col<KIND, CONSTR, MASK, NW, P, true, HIST>(J, H, sBeta, sBot, sTop);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent dataflow kernel (see FgpFlowArgs). Memory ordering: the dual
+// state, the only data that passes between tasks, is read and written with
+// agent-scope (device-coherent) atomic accesses, which the 8 XCDs' separate L2
+// caches keep coherent. A task waits for all of its own memory operations to
+// complete (every wave) and crosses a workgroup barrier before raising its
+// done flag; a waiting task polls its neighbours' flags with agent-scope atomic
+// loads and crosses a barrier before loading. Every wait is bounded: after kFlowSpin
+// polls (about a second) it records the failure in *err and proceeds, and
+// every other wait then stops at its next check, so the grid always drains.
+constexpr int kFlowSpin = 1 << 20;
+
+template <int KIND, int CONSTR, bool MASK>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void fgp_flow_kernel(FgpFlowArgs A) {
+  constexpr int NW = 8, P = 8;
+  __shared__ float2 sBot[NW * kRW];
+  __shared__ float2 sTop[NW * kRW];
+  __shared__ float sBeta[kMaxFuse];
+  __shared__ int sTicket;
+  const int per_img = A.tiles_x * A.tiles_y;
+  const int per_step = per_img * A.batch;
+  const int total = per_step * (A.steps + 1);
+  const long long px = (long long)A.m * A.n;
+  const int H = A.halo;
+  for (;;) {
+    __syncthreads();  // the previous task is done with LDS
+    if (threadIdx.x == 0) sTicket = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int ticket = sTicket;
+    if (ticket >= total) break;
+    const int st = ticket / per_step;
+    const int rem = ticket - st * per_step;
+    const int img = rem / per_img;
+    const int t = rem - img * per_img;
+    const int ty = t / A.tiles_x;
+    const int tx = t - ty * A.tiles_x;
+    int* done_img = A.done + (long long)img * per_img;
+    if (st > 0) {
+      if (threadIdx.x < 9) {
+        const int ny = ty + (int)threadIdx.x / 3 - 1, nx = tx + (int)threadIdx.x % 3 - 1;
+        if (ny >= 0 && ny < A.tiles_y && nx >= 0 && nx < A.tiles_x) {
+          const int* flag = done_img + ny * A.tiles_x + nx;
+          int spins = 0;
+          while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < st) {
+            if (++spins > kFlowSpin) {
+              __hip_atomic_store(A.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            // once any wait has given up, stop waiting everywhere so the grid drains at once
+            if ((spins & 63) == 0 && __hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const bool epi = (st == A.steps);
+    const int T = epi ? 0 : (st == A.steps - 1 ? A.T_last : A.T);
+    if (threadIdx.x < kMaxFuse) sBeta[threadIdx.x] = ((int)threadIdx.x < T) ? A.beta[st * A.T + threadIdx.x] : 0.0f;
+    __syncthreads();
+    float* in_buf = (st % 2 == 0) ? A.buf0 : A.buf1;
+    float* out_buf = (st % 2 == 0) ? A.buf1 : A.buf0;
+    const float* src = (st == 0) ? A.st_in : in_buf;
+    float* dst = epi ? A.st_out : out_buf;
+    TileJob J;
+    J.b = reinterpret_cast<const float2*>(A.b) + img * px;
+    J.mask = A.mask;
+    J.st_in = src ? reinterpret_cast<const float4*>(src) + img * 2 * px : nullptr;
+    J.st_out = dst ? reinterpret_cast<float4*>(dst) + img * 2 * px : nullptr;
+    J.x = epi ? reinterpret_cast<float2*>(A.x) + img * px : nullptr;
+    J.m = A.m;
+    J.n = A.n;
+    J.ty = ty;
+    J.tx = tx;
+    J.lam = A.lam[img];
+    J.c = A.c[img];
+    J.R = A.R;
+    J.T = T;
+    J.r_hist = nullptr;
+    J.hist_stride = 0;
+    const int c0 = tx * (kRW - 2 * H) - H, r0 = ty * (NW * P - 2 * H) - H;
+    const bool interior = c0 >= 1 && c0 + kRW <= J.n - 1 && r0 >= 1 && r0 + NW * P <= J.m - 1;
+    if (interior)
+      fgp_tile_col<KIND, CONSTR, MASK, NW, P, false, false, true>(J, H, sBeta, sBot, sTop);
+    else
+      fgp_tile_col<KIND, CONSTR, MASK, NW, P, true, false, true>(J, H, sBeta, sBot, sTop);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's state stores are complete (device-coherent)
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(done_img + t, st + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -616,6 +735,43 @@ hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const T
     case K2I: return launch_plain_kind<K2I>(a, constr, mask, rh, nblocks, s);
     default: return launch_plain_kind<K2A>(a, constr, mask, rh, nblocks, s);
   }
+}
+
+template <int KIND>
+static const void* flow_kernel_ptr(int constr, bool mask) {
+  if (constr == C_MOD)
+    return mask ? reinterpret_cast<const void*>(&fgp_flow_kernel<KIND, C_MOD, true>)
+                : reinterpret_cast<const void*>(&fgp_flow_kernel<KIND, C_MOD, false>);
+  return mask ? reinterpret_cast<const void*>(&fgp_flow_kernel<KIND, C_NONE, true>)
+              : reinterpret_cast<const void*>(&fgp_flow_kernel<KIND, C_NONE, false>);
+}
+
+long long flow_ints(int batch, int m, int n, int h) {
+  const long long tx = (n + (kRW - 2 * h) - 1) / (kRW - 2 * h);
+  const long long ty = (m + (64 - 2 * h) - 1) / (64 - 2 * h);
+  return 64 + (long long)batch * tx * ty;
+}
+
+hipError_t launch_fgp_flow(const FgpFlowArgs& a, int kind, int constr, hipStream_t s) {
+  const bool mask = a.mask != nullptr;
+  const void* fn = nullptr;
+  switch (kind) {
+    case K1I: fn = flow_kernel_ptr<K1I>(constr, mask); break;
+    case K1A: fn = flow_kernel_ptr<K1A>(constr, mask); break;
+    case K2I: fn = flow_kernel_ptr<K2I>(constr, mask); break;
+    default: fn = flow_kernel_ptr<K2A>(constr, mask); break;
+  }
+  // One workgroup per resident slot: a ticket is only taken by a running
+  // workgroup, and every task waits only on tasks with smaller tickets.
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, 0);
+  if (e != hipSuccess) return e;
+  const long long total = (long long)a.tiles_x * a.tiles_y * a.batch * (a.steps + 1);
+  const int grid = (int)std::max(1LL, std::min<long long>((long long)std::max(per_cu, 1) * cus, total));
+  void* args[] = {const_cast<FgpFlowArgs*>(&a)};
+  return hipLaunchKernel(fn, dim3(grid), dim3(512), args, 0, s);
 }
 
 const void* fgp_batched_kernel_ptr(int constr, const TileShape& ts) {

@@ -187,3 +187,45 @@ def test_gradient_projection_method_matches_oracle(kind):
 def test_unknown_method_is_rejected():
     with pytest.raises(ValueError):
         ctv().denoise(dev(case((8, 8), 1)), 0.1, method="newton")
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_dataflow_schedule_is_bitwise_identical(kind):
+    """The persistent dataflow launch and the one-launch-per-step schedule run
+    the same tile function on the same halos: results, final states and gaps
+    agree bit for bit (masked, ragged, batch across the 32-image chunk)."""
+    rng = np.random.default_rng(41)
+    cases = [((203, 141), 1, 37, True), ((64, 64), 3, 20, False), ((1, 300), 1, 17, False),
+             ((300, 1), 2, 9, False), ((130, 150), 34, 12, True)]
+    for shape, B, K, masked in cases:
+        bs = np.stack([case(shape, 50 + i) * 1.3 for i in range(B)]).astype(np.complex64)
+        mask = dev(synth.square_mask(shape[0], shape[1], 0.6, rng)) if masked else None
+        lams = list(np.linspace(0.03, 0.2, B))
+        out = {}
+        for sched in ("steps", "flow"):
+            x, g, stt = ctv().denoise(dev(bs), lams, kind=kind, iters=K, support=mask, gap=True, return_state=True,
+                                      schedule=sched)
+            out[sched] = (x.cpu().numpy(), g.cpu().numpy(), stt.cpu().numpy())
+        for a, b in zip(out["steps"], out["flow"]):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (kind, shape, B, K)
+
+
+def test_dataflow_resume_and_long_runs():
+    """Resume from a state and runs longer than one persistent launch (several
+    chunks of whole fused steps) stay bitwise equal to the per-step schedule
+    and to the oracle."""
+    b = case((96, 90), 23)
+    bt = dev(b)
+    x_steps = ctv().denoise(bt, 0.05, kind="2i", iters=1001, schedule="steps").cpu().numpy()
+    x_flow = ctv().denoise(bt, 0.05, kind="2i", iters=1001, schedule="flow").cpu().numpy()
+    assert np.array_equal(x_steps.view(np.uint32), x_flow.view(np.uint32))
+    _, st = ctv().denoise(bt, 0.05, kind="2i", iters=333, schedule="flow", return_state=True)
+    x_res = ctv().denoise(bt, 0.05, kind="2i", iters=668, state=st, k0=333, schedule="flow").cpu().numpy()
+    assert np.array_equal(x_res.view(np.uint32), x_flow.view(np.uint32))
+    xo = tv.fgp(b.astype(np.complex128), 0.05, 1001, "2i")
+    assert rel(x_flow, xo) <= TOL
+
+
+def test_dataflow_schedule_rejects_checkpoints():
+    with pytest.raises(Exception):
+        ctv().denoise(dev(case((32, 32), 1)), 0.1, iters=20, ckpt_every=5, schedule="flow")
