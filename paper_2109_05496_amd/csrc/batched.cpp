@@ -1,6 +1,7 @@
 // Batched ragged denoising: a plan holds the device descriptor table, the
 // float64-derived momentum table, one tile list per fused step and a HIP graph
-// with one persistent-grid kernel node per step. Executing the plan is one
+// with one kernel node per step (one workgroup per tile of the step, so the
+// hardware dispatcher balances the load). Executing the plan is one
 // hipGraphLaunch; pointers that change between calls are patched into the
 // instantiated graph.
 #include <hip/hip_runtime.h>
@@ -35,7 +36,6 @@ struct ctv_batched_plan {
   hipGraphExec_t exec = nullptr;
   const void* func = nullptr;
   int block = 0;
-  int grid_cap = 0;
   const float* b = nullptr;
   const uint8_t* support = nullptr;
   float* x = nullptr;
@@ -79,7 +79,7 @@ hipKernelNodeParams node_params(ctv_batched_plan* p, size_t s, void** kp) {
   hipKernelNodeParams np;
   std::memset(&np, 0, sizeof(np));
   np.func = const_cast<void*>(p->func);
-  np.gridDim = dim3((unsigned)std::max(1, std::min(p->step_count[s], p->grid_cap)));
+  np.gridDim = dim3((unsigned)std::max(1, p->step_count[s]));
   np.blockDim = dim3((unsigned)p->block);
   np.sharedMemBytes = 0;
   np.kernelParams = kp;
@@ -202,15 +202,10 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_beta, beta.data(), beta.size() * sizeof(float), hipMemcpyHostToDevice);
-  int dev = 0, cus = 0, per_cu = 0;
-  if (e == hipSuccess) e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p->func, p->block, 0);
   if (e != hipSuccess) {
     release(p);
     return hip_fail(e, "batched plan setup");
   }
-  p->grid_cap = std::max(8, cus * std::max(per_cu, 1));
   p->args.resize((size_t)steps);
   *plan_out = p;
   return CTV_OK;

@@ -249,6 +249,10 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
   // dual state through device-coherent accesses, which on MI355X cost more
   // (2048^2, K = 200: 279 vs 346 G px-it/s) than the launch tail it removes.
   const bool use_flow = flow_ok && p->schedule == CTV_S_FLOW;
+  // an image that fits in one 8 x 8 column tile runs without a halo, all
+  // iterations of a chunk in one launch (same results as per-step launches)
+  const bool use_single = !use_flow && p->schedule == CTV_S_AUTO && ckpt_every == 0 && m <= 64 && n <= 64 &&
+                          tl.shape.waves == 8 && tl.shape.rows_per_thread == 8;
   std::vector<float> beta;
   momentum_table(p->method, k0 + p->iters + 1, beta);
   const Radii R = make_radii(p->tv_kind, p->alpha);
@@ -260,7 +264,33 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
     const float* src = state_in ? state_in + st_off : nullptr;
     int k = k0;
     const int kend = k0 + p->iters;
-    if (use_flow) {
+    if (use_single) {
+      do {
+        const int Kc = std::min(kFlowMaxIters, kend - k);
+        const bool last = (k + Kc == kend);
+        FgpSingleArgs sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.b = b + 2 * img_px;
+        sa.mask = support;
+        sa.st_in = src;
+        float* other = (src == bufA + st_off) ? bufB + st_off : bufA + st_off;
+        sa.st_out = last ? (state_out ? state_out + st_off : (gap ? other : nullptr)) : other;
+        sa.x = last ? x + 2 * img_px : nullptr;
+        sa.m = m;
+        sa.n = n;
+        sa.T = Kc;
+        sa.R = R;
+        for (int i = 0; i < cb; ++i) {
+          sa.lam[i] = lambda_host[c0 + i];
+          sa.c[i] = step_of(lambda_host[c0 + i]);
+        }
+        for (int i = 0; i < Kc; ++i) sa.beta[i] = beta[(size_t)(k + 1 + i)];
+        hipError_t e = launch_fgp_single(sa, p->tv_kind, p->constraint, cb, s);
+        if (e != hipSuccess) return hip_fail(e, "fgp single-tile launch");
+        src = sa.st_out;
+        k += Kc;
+      } while (k < kend);
+    } else if (use_flow) {
       // chunks of whole fused steps, each one persistent launch
       const int chunk_iters = (kFlowMaxIters / tl.T) * tl.T;
       while (k < kend) {

@@ -57,6 +57,23 @@ struct FgpFlowArgs {
   float beta[kFlowMaxIters];  // beta[i]: momentum of the i-th iteration of this launch
 };
 hipError_t launch_fgp_flow(const FgpFlowArgs& a, int kind, int constr, hipStream_t s);
+
+// Images that fit in one 8 x 8 column tile (m, n <= 64) have no neighbouring
+// tiles, hence no halo: one workgroup per image runs up to kFlowMaxIters
+// iterations in a single launch.
+struct FgpSingleArgs {
+  const float* b;         // chunk base, complex64
+  const uint8_t* mask;    // [m][n] or nullptr
+  const float* st_in;     // [chunk][2][m][n][4] or nullptr (cold start)
+  float* st_out;          // same layout or nullptr
+  float* x;               // complex64 output or nullptr
+  int m, n, T;
+  Radii R;
+  float lam[kPlainChunk];
+  float c[kPlainChunk];
+  float beta[kFlowMaxIters];
+};
+hipError_t launch_fgp_single(const FgpSingleArgs& a, int kind, int constr, int batch, hipStream_t s);
 // Ints of flow bookkeeping (counter, error flag, done flags) for `batch` images of m x n at halo h.
 long long flow_ints(int batch, int m, int n, int h);
 

@@ -464,6 +464,36 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void f
 }
 
 // ---------------------------------------------------------------------------
+// Whole image in one tile (see FgpSingleArgs): halo 0, every row always live.
+template <int KIND, int CONSTR, bool MASK>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void fgp_single_kernel(FgpSingleArgs A) {
+  __shared__ float2 sBot[8 * kRW];
+  __shared__ float2 sTop[8 * kRW];
+  __shared__ float sBeta[kFlowMaxIters];
+  for (int i = threadIdx.x; i < A.T; i += blockDim.x) sBeta[i] = A.beta[i];
+  __syncthreads();
+  const int img = blockIdx.x;
+  const long long px = (long long)A.m * A.n;
+  TileJob J;
+  J.b = reinterpret_cast<const float2*>(A.b) + img * px;
+  J.mask = A.mask;
+  J.st_in = A.st_in ? reinterpret_cast<const float4*>(A.st_in) + img * 2 * px : nullptr;
+  J.st_out = A.st_out ? reinterpret_cast<float4*>(A.st_out) + img * 2 * px : nullptr;
+  J.x = A.x ? reinterpret_cast<float2*>(A.x) + img * px : nullptr;
+  J.m = A.m;
+  J.n = A.n;
+  J.tx = 0;
+  J.ty = 0;
+  J.lam = A.lam[img];
+  J.c = A.c[img];
+  J.R = A.R;
+  J.T = A.T;
+  J.r_hist = nullptr;
+  J.hist_stride = 0;
+  fgp_tile_col<KIND, CONSTR, MASK, 8, 8, true>(J, 0, sBeta, sBot, sTop);
+}
+
+// ---------------------------------------------------------------------------
 // Plain kernel: `batch` images of one shape, one parameter set.
 // ---------------------------------------------------------------------------
 template <int KIND, int CONSTR, bool MASK, int RH>
@@ -503,8 +533,10 @@ __global__ __launch_bounds__(kThreads) void fgp_plain_kernel(FgpPlainArgs P) {
 // ragged batch. The tile list of the step holds, per image still running, the
 // tiles laid out for that image's own halo (T_i + 1 when its last iteration
 // falls in this step, else T_i), so each image is computed exactly as a plain
-// call would. Persistent grid: each XCD owns one contiguous slice of the tile
-// list and its workgroups stride through it.
+// call would. Each XCD owns one contiguous slice of the tile list and its
+// workgroups stride through it; the plan launches one workgroup per tile (a
+// persistent grid with static striding measured 15-20 % slower than letting
+// the hardware dispatcher balance), so the loop normally runs once.
 // ---------------------------------------------------------------------------
 template <int CONSTR, int NW, int P>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void fgp_batched_kernel(FgpBatchedArgs A) {
@@ -744,6 +776,29 @@ static const void* flow_kernel_ptr(int constr, bool mask) {
                 : reinterpret_cast<const void*>(&fgp_flow_kernel<KIND, C_MOD, false>);
   return mask ? reinterpret_cast<const void*>(&fgp_flow_kernel<KIND, C_NONE, true>)
               : reinterpret_cast<const void*>(&fgp_flow_kernel<KIND, C_NONE, false>);
+}
+
+template <int KIND>
+static hipError_t launch_single_kind(const FgpSingleArgs& a, int constr, int batch, hipStream_t s) {
+  const bool mask = a.mask != nullptr;
+  if (constr == C_MOD) {
+    if (mask) hipLaunchKernelGGL((fgp_single_kernel<KIND, C_MOD, true>), dim3(batch), dim3(512), 0, s, a);
+    else hipLaunchKernelGGL((fgp_single_kernel<KIND, C_MOD, false>), dim3(batch), dim3(512), 0, s, a);
+  } else {
+    if (mask) hipLaunchKernelGGL((fgp_single_kernel<KIND, C_NONE, true>), dim3(batch), dim3(512), 0, s, a);
+    else hipLaunchKernelGGL((fgp_single_kernel<KIND, C_NONE, false>), dim3(batch), dim3(512), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fgp_single(const FgpSingleArgs& a, int kind, int constr, int batch, hipStream_t s) {
+  if (a.m > 64 || a.n > kRW || a.T < 0 || a.T > kFlowMaxIters) return hipErrorInvalidValue;
+  switch (kind) {
+    case K1I: return launch_single_kind<K1I>(a, constr, batch, s);
+    case K1A: return launch_single_kind<K1A>(a, constr, batch, s);
+    case K2I: return launch_single_kind<K2I>(a, constr, batch, s);
+    default: return launch_single_kind<K2A>(a, constr, batch, s);
+  }
 }
 
 long long flow_ints(int batch, int m, int n, int h) {

@@ -229,3 +229,28 @@ def test_dataflow_resume_and_long_runs():
 def test_dataflow_schedule_rejects_checkpoints():
     with pytest.raises(Exception):
         ctv().denoise(dev(case((32, 32), 1)), 0.1, iters=20, ckpt_every=5, schedule="flow")
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_single_tile_images_match_per_step_launches(kind):
+    """Images of at most 64 x 64 run all iterations in one launch without a halo;
+    results, states and gaps equal the per-step launches bit for bit, also
+    beyond one launch (500 iterations) and when resumed."""
+    rng = np.random.default_rng(61)
+    for shape, B, K, masked in [((64, 64), 1, 100, False), ((37, 53), 3, 23, True), ((1, 1), 2, 5, False),
+                                ((1, 64), 1, 500, False), ((64, 9), 1, 17, True)]:
+        bs = np.stack([case(shape, 70 + i) * 1.3 for i in range(B)]).astype(np.complex64)
+        mask = dev(synth.square_mask(shape[0], shape[1], 0.6, rng)) if masked else None
+        lams = list(np.linspace(0.04, 0.15, B))
+        out = {}
+        for sched in ("steps", "auto"):
+            x, g, stt = ctv().denoise(dev(bs), lams, kind=kind, iters=K, support=mask, gap=True, return_state=True,
+                                      schedule=sched)
+            out[sched] = (x.cpu().numpy(), g.cpu().numpy(), stt.cpu().numpy())
+        for a, b in zip(out["steps"], out["auto"]):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (kind, shape, B, K)
+    b = case((40, 50), 3)
+    full = ctv().denoise(dev(b), 0.07, kind=kind, iters=30).cpu().numpy()
+    _, st = ctv().denoise(dev(b), 0.07, kind=kind, iters=12, return_state=True)
+    res = ctv().denoise(dev(b), 0.07, kind=kind, iters=18, state=st, k0=12).cpu().numpy()
+    assert np.array_equal(res.view(np.uint32), full.view(np.uint32))
