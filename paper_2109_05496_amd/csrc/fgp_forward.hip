@@ -465,10 +465,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void f
 
 // ---------------------------------------------------------------------------
 // Whole image in one tile (see FgpSingleArgs): halo 0, every row always live.
+// 16 waves x 4 rows: the same 64 x 64 region as the 8 x 8 tile with half the
+// rows per wave, i.e. shorter dependent chains for this latency-bound case.
+constexpr int kSingleNW = 16, kSingleP = 4;
+
 template <int KIND, int CONSTR, bool MASK>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void fgp_single_kernel(FgpSingleArgs A) {
-  __shared__ float2 sBot[8 * kRW];
-  __shared__ float2 sTop[8 * kRW];
+__global__ __launch_bounds__(kSingleNW * 64) void fgp_single_kernel(FgpSingleArgs A) {
+  __shared__ float2 sBot[kSingleNW * kRW];
+  __shared__ float2 sTop[kSingleNW * kRW];
   __shared__ float sBeta[kFlowMaxIters];
   for (int i = threadIdx.x; i < A.T; i += blockDim.x) sBeta[i] = A.beta[i];
   __syncthreads();
@@ -490,7 +494,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void f
   J.T = A.T;
   J.r_hist = nullptr;
   J.hist_stride = 0;
-  fgp_tile_col<KIND, CONSTR, MASK, 8, 8, true>(J, 0, sBeta, sBot, sTop);
+  fgp_tile_col<KIND, CONSTR, MASK, kSingleNW, kSingleP, true>(J, 0, sBeta, sBot, sTop);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,17 +786,17 @@ template <int KIND>
 static hipError_t launch_single_kind(const FgpSingleArgs& a, int constr, int batch, hipStream_t s) {
   const bool mask = a.mask != nullptr;
   if (constr == C_MOD) {
-    if (mask) hipLaunchKernelGGL((fgp_single_kernel<KIND, C_MOD, true>), dim3(batch), dim3(512), 0, s, a);
-    else hipLaunchKernelGGL((fgp_single_kernel<KIND, C_MOD, false>), dim3(batch), dim3(512), 0, s, a);
+    if (mask) hipLaunchKernelGGL((fgp_single_kernel<KIND, C_MOD, true>), dim3(batch), dim3(kSingleNW * 64), 0, s, a);
+    else hipLaunchKernelGGL((fgp_single_kernel<KIND, C_MOD, false>), dim3(batch), dim3(kSingleNW * 64), 0, s, a);
   } else {
-    if (mask) hipLaunchKernelGGL((fgp_single_kernel<KIND, C_NONE, true>), dim3(batch), dim3(512), 0, s, a);
-    else hipLaunchKernelGGL((fgp_single_kernel<KIND, C_NONE, false>), dim3(batch), dim3(512), 0, s, a);
+    if (mask) hipLaunchKernelGGL((fgp_single_kernel<KIND, C_NONE, true>), dim3(batch), dim3(kSingleNW * 64), 0, s, a);
+    else hipLaunchKernelGGL((fgp_single_kernel<KIND, C_NONE, false>), dim3(batch), dim3(kSingleNW * 64), 0, s, a);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_fgp_single(const FgpSingleArgs& a, int kind, int constr, int batch, hipStream_t s) {
-  if (a.m > 64 || a.n > kRW || a.T < 0 || a.T > kFlowMaxIters) return hipErrorInvalidValue;
+  if (a.m > kSingleNW * kSingleP || a.n > kRW || a.T < 0 || a.T > kFlowMaxIters) return hipErrorInvalidValue;
   switch (kind) {
     case K1I: return launch_single_kind<K1I>(a, constr, batch, s);
     case K1A: return launch_single_kind<K1A>(a, constr, batch, s);
