@@ -254,3 +254,27 @@ def test_single_tile_images_match_per_step_launches(kind):
     _, st = ctv().denoise(dev(b), 0.07, kind=kind, iters=12, return_state=True)
     res = ctv().denoise(dev(b), 0.07, kind=kind, iters=18, state=st, k0=12).cpu().numpy()
     assert np.array_equal(res.view(np.uint32), full.view(np.uint32))
+
+
+def test_config2_full_size_against_oracle_on_corner_crops():
+    """The benchmark's workload at full size (masked 2048^2, four kinds, K = 200,
+    default launch configuration): x after K iterations depends on b only
+    within Chebyshev distance K + 1 (pinned on the CPU), so the oracle run on a
+    corner crop gives the exact full-image answer on every pixel at least K + 2
+    from the crop's cut edges. Two opposite corners cover all four image
+    borders and the support edge."""
+    c = synth.config2(0)
+    b, mask, K = c["b"], c["mask"], c["iters"]
+    m, n = b.shape
+    S, margin = 440, K + 2
+    bt, mt = dev(b), dev(mask)
+    for kind in c["kinds"]:
+        x = ctv().denoise(bt, c["lam"], kind=kind, alpha=c["alpha"], support=mt, iters=K).cpu().numpy()
+        for r0, c0 in ((0, 0), (m - S, n - S)):
+            xo = tv.fgp(b[r0:r0 + S, c0:c0 + S].astype(np.complex128), c["lam"], K, kind, c["alpha"], "modulus",
+                        mask[r0:r0 + S, c0:c0 + S])
+            rs = slice(0, S - margin) if r0 == 0 else slice(margin, S)
+            cs = slice(0, S - margin) if c0 == 0 else slice(margin, S)
+            got = x[r0:r0 + S, c0:c0 + S][rs, cs]
+            assert rel(got, xo[rs, cs]) <= TOL, (kind, r0, rel(got, xo[rs, cs]))
+            assert rel(got, xo[rs, cs]) <= GUARD, (kind, r0, rel(got, xo[rs, cs]))

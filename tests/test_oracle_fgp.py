@@ -231,3 +231,22 @@ def test_gradient_projection_variant(kind, rng):
     prob = pdhg.Problem(bc, 0.3, kind, 0.5)
     assert prob.certificate(pdhg.to_vec(xg), pdhg.dual_to_vec(q, 0.3)) <= 1e-10
     assert np.abs(tv.fgp(bc, 0.3, 15, kind, method="gp") - tv.fgp(bc, 0.3, 15, kind)).max() > 1e-6
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_dependence_radius_is_one_pixel_per_iteration(kind, rng):
+    """x after K iterations depends on b only within Chebyshev distance K + 1:
+    on a corner crop the oracle reproduces the full-image result wherever the
+    pixel is at least K + 2 away from the cut edges (the basis of the sampled
+    full-size parity checks), and not everywhere (the bound is not vacuous)."""
+    b = rand_img((40, 44), rng, 1.2)
+    mask = (rng.random((40, 44)) > 0.2).astype(np.uint8)
+    K, lam = 6, 0.3
+    full = tv.fgp(b, lam, K, kind, 0.4, "modulus", mask)
+    for (r0, r1, c0, c1) in ((0, 22, 0, 25), (17, 40, 20, 44)):
+        crop = tv.fgp(b[r0:r1, c0:c1], lam, K, kind, 0.4, "modulus", mask[r0:r1, c0:c1])
+        m = K + 2
+        rs = slice(0 if r0 == 0 else m, (r1 - r0) if r1 == 40 else (r1 - r0) - m)
+        cs = slice(0 if c0 == 0 else m, (c1 - c0) if c1 == 44 else (c1 - c0) - m)
+        np.testing.assert_allclose(crop[rs, cs], full[r0:r1, c0:c1][rs, cs], atol=1e-13)
+        assert np.abs(crop - full[r0:r1, c0:c1]).max() > 1e-8
