@@ -278,3 +278,28 @@ def test_config2_full_size_against_oracle_on_corner_crops():
             got = x[r0:r0 + S, c0:c0 + S][rs, cs]
             assert rel(got, xo[rs, cs]) <= TOL, (kind, r0, rel(got, xo[rs, cs]))
             assert rel(got, xo[rs, cs]) <= GUARD, (kind, r0, rel(got, xo[rs, cs]))
+
+
+@pytest.mark.parametrize("kind", ["2i", "2a"])
+@pytest.mark.parametrize("alpha", [0.0, 1.0])
+def test_type2_degenerate_weights_match_oracle(kind, alpha):
+    """alpha in {0, 1} gives one channel a zero-radius dual ball (its TV weight
+    vanishes): that channel is only projected, the other is fully regularised."""
+    b = (case((45, 70), 31) * 1.3).astype(np.complex64)
+    x = gpu_denoise(b, 0.1, kind=kind, alpha=alpha, iters=40)
+    xo = tv.fgp(b.astype(np.complex128), 0.1, 40, kind, alpha)
+    assert rel(x, xo) <= TOL
+    assert rel(x, xo) <= GUARD
+
+
+def test_empty_support_and_large_lambda():
+    """An all-zero support gives x = 0 exactly; a very large lambda drives the
+    unmasked solution towards the projected mean, as the oracle does."""
+    b = case((50, 60), 32)
+    zero = np.zeros((50, 60), np.uint8)
+    x = ctv().denoise(dev(b), 0.2, iters=30, support=dev(zero)).cpu().numpy()
+    assert np.all(x == 0)
+    for kind in tv.KINDS:
+        x = gpu_denoise(b, 50.0, kind=kind, iters=60)
+        xo = tv.fgp(b.astype(np.complex128), 50.0, 60, kind)
+        assert rel(x, xo) <= TOL, kind
