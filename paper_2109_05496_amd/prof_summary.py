@@ -47,9 +47,15 @@ def _largest(v):
     return _mean([x for x in v if x >= 0.9 * top])
 
 
-def stats(csv_path, out, cmd):
+def stats(csv_path, out, cmd, match=None, title=None):
     rows = list(csv.DictReader(open(csv_path)))
-    lines = ["# rocprofv3 kernel statistics", "", f"Command: `{cmd}`", "",
+    if match:
+        keys = match.split("|")
+        rows = [r for r in rows if any(k in r["Name"] for k in keys)]
+    head = ["# rocprofv3 kernel statistics" + (f": {title}" if title else ""), ""]
+    if match:
+        head += [f"Kernels whose name contains: {', '.join('`%s`' % k for k in match.split('|'))}.", ""]
+    lines = head + [f"Command: `{cmd}`", "",
              "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
     for r in rows:
         lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
@@ -113,6 +119,8 @@ if __name__ == "__main__":
     s.add_argument("csv")
     s.add_argument("out")
     s.add_argument("--cmd", required=True)
+    s.add_argument("--match", default=None, help="'|'-separated substrings of the kernel names to keep")
+    s.add_argument("--title", default=None)
     p = sub.add_parser("pmc")
     p.add_argument("fetch")
     p.add_argument("write")
@@ -121,6 +129,6 @@ if __name__ == "__main__":
     p.add_argument("--cmd", required=True)
     a = ap.parse_args()
     if a.what == "stats":
-        stats(a.csv, a.out, a.cmd)
+        stats(a.csv, a.out, a.cmd, a.match, a.title)
     else:
         pmc(a.fetch, a.write, a.valu, a.out, a.cmd)
