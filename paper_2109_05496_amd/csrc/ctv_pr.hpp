@@ -37,6 +37,12 @@ bool fft_size_ok(int v);
 int fft_line_blocks(int N, long long lines);
 hipError_t launch_fft_lines(FftArgs a, int N, long long lines, int dir, int batch, hipStream_t s);
 hipError_t launch_transpose(const float2* in, float2* out, int R, int C, int batch, hipStream_t s);
+// Second pass of a 2-D transform: input images [N][W] (a.in, stride a.in_stride),
+// FFT along the N-long columns, output transposed [W][N] (a.out / epilogue in
+// that layout): one column-pass launch; for N <= 16 and for the accumulate-all
+// epilogue a transpose into tmp (N * W elements per image) and a line pass.
+hipError_t launch_fft_second(FftArgs a, int N, long long W, int dir, int batch, float2* tmp, hipStream_t s);
+int fft_second_blocks(int N, long long W);
 hipError_t launch_twiddles(float2* tw, int N, hipStream_t s);
 hipError_t launch_transfer_t(float2* Ht, int m, int n, double dist, double wavelength, double pixel, hipStream_t s);
 hipError_t launch_sqrt_y(const float* y, float* sy, float2* syc, long long total, hipStream_t s);

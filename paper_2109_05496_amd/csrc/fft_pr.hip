@@ -182,7 +182,9 @@ __device__ __forceinline__ void pass_lds(const float2* L, float2 (&v)[16], int j
 
 // The FFT of one line (image `img`, line `line`) up to the last pass, whose 16
 // outputs per thread are returned in o[] with their positions within the line.
-template <int N, int DIR>
+// FROM_LDS: the line is already staged in sl (natural order, pidx positions)
+// and the first pass reads it from there instead of global memory.
+template <int N, int DIR, bool FROM_LDS = false>
 __device__ __forceinline__ void line_fft(const FftArgs& a, int img, long long line, bool live, float2* sl,
                                          float2 (&o)[16], int (&pos)[16]) {
   constexpr int TPL = N / 16;                  // threads per line
@@ -196,7 +198,10 @@ __device__ __forceinline__ void line_fft(const FftArgs& a, int img, long long li
   const float2* in = a.in + (long long)img * a.in_stride;
   float2 v[16];
   // pass 1: radix 16 straight from global memory (Ns = 1, no twiddles)
-  if (live) {
+  if (FROM_LDS) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = sl[pidx(lt + r * TPL)];
+  } else if (live) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = pre_op(a, img, rowbase + lt + r * TPL, in[rowbase + lt + r * TPL]);
   } else {
@@ -347,6 +352,62 @@ __global__ __launch_bounds__(kThreads) void fft_small_kernel(FftArgs a) {
   if (a.post == kPostResidual) {
     const double tot = block_sum(loss, red);
     if (threadIdx.x == 0) a.partial[(long long)img * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+// Column pass: input image [N][W] (W = a.lines columns, rows contiguous), an
+// FFT along every N-long column, column c written as line c of the output, so
+// the output image is the transposed [W][N] - a line pass fused with the
+// transpose. CB columns per block are staged through LDS with row-contiguous
+// loads (CB * 8 bytes per row); the radix passes then run as in line_fft and
+// each column's result is stored as one contiguous line. Same epilogues as the
+// line kernel, indexed in the output layout (no pre-multiply, no
+// accumulate-all). 8 columns per block (two blocks per CU at N = 1024)
+// measured faster than 16 (one block per CU) or 4 (32-byte row segments).
+template <int N>
+constexpr int col_block() { return (512 / (N / 16)) < 8 ? (512 / (N / 16)) : 8; }
+
+template <int N, int DIR>
+__global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_kernel(FftArgs a) {
+  constexpr int TPL = N / 16;
+  constexpr int CB = col_block<N>();
+  constexpr int NT = CB * TPL;
+  constexpr int LS = N + N / 16 + 1;  // padded line; the odd pitch spreads the staging writes over banks
+  __shared__ float2 s[CB * LS];
+  __shared__ double red[(NT + 63) / 64];
+  const long long W = a.lines;
+  const int cl = threadIdx.x / TPL;
+  const long long col = (long long)blockIdx.x * CB + cl;
+  const bool live = col < W;
+  float2* sl = s + cl * LS;
+  const int img = blockIdx.y;
+  {
+    const float2* in = a.in + (long long)img * a.in_stride;
+    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+      const int row = idx / CB, c = idx - (idx / CB) * CB;
+      const long long gc = (long long)blockIdx.x * CB + c;
+      s[c * LS + pidx(row)] = gc < W ? in[(long long)row * W + gc] : make_float2(0.0f, 0.0f);
+    }
+    __syncthreads();
+  }
+  float2 o[16];
+  int pos[16];
+  line_fft<N, DIR, true>(a, img, col, live, sl, o, pos);
+  double loss = 0.0;
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) post_op(a, img, col * N + pos[r], o[r], loss);
+  }
+  if (a.post == kPostResidual) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (NT + 63) / 64; ++w) t += red[w];
+      a.partial[(long long)img * gridDim.x + blockIdx.x] = t;
+    }
   }
 }
 
@@ -531,6 +592,44 @@ hipError_t launch_fft_lines(FftArgs a, int N, long long lines, int dir, int batc
   if (a.post == kPostAccumulateAll)  // the images are looped inside the kernel
     return dir < 0 ? launch_line_dir<-1, true>(a, N, 1, s) : launch_line_dir<1, true>(a, N, 1, s);
   return dir < 0 ? launch_line_dir<-1, false>(a, N, batch, s) : launch_line_dir<1, false>(a, N, batch, s);
+}
+
+template <int DIR>
+static hipError_t launch_col_dir(const FftArgs& a, int N, int batch, hipStream_t s) {
+#define CTV_COLK(NN)                                                                   \
+  case NN: {                                                                           \
+    constexpr int cb = col_block<NN>();                                                \
+    const dim3 grid((unsigned)((a.lines + cb - 1) / cb), (unsigned)batch);             \
+    hipLaunchKernelGGL((fft_col_kernel<NN, DIR>), grid, dim3(cb * (NN / 16)), 0, s, a); \
+    break;                                                                             \
+  }
+  switch (N) {
+    CTV_COLK(32) CTV_COLK(64) CTV_COLK(128) CTV_COLK(256) CTV_COLK(512) CTV_COLK(1024) CTV_COLK(2048) CTV_COLK(4096)
+    default: return hipErrorInvalidValue;
+  }
+#undef CTV_COLK
+  return hipGetLastError();
+}
+
+int fft_second_blocks(int N, long long W) {
+  if (N <= 16) return fft_line_blocks(N, W);
+  const int cb = (512 / (N / 16)) < 8 ? (512 / (N / 16)) : 8;  // col_block<N>
+  return (int)((W + cb - 1) / cb);
+}
+
+hipError_t launch_fft_second(FftArgs a, int N, long long W, int dir, int batch, float2* tmp, hipStream_t s) {
+  if (N <= 16 || a.post == kPostAccumulateAll) {
+    // transpose into tmp, then a line pass with the same epilogue: short
+    // columns, and the accumulate-all epilogue (its images are looped inside
+    // one block, which measured faster on line blocks than on staged columns)
+    hipError_t e = launch_transpose(a.in, tmp, N, (int)W, a.post == kPostAccumulateAll ? a.n_acc : batch, s);
+    if (e != hipSuccess) return e;
+    a.in = tmp;
+    return launch_fft_lines(a, N, W, dir, batch, s);
+  }
+  if (a.pre != kPreNone) return hipErrorInvalidValue;
+  a.lines = W;
+  return dir < 0 ? launch_col_dir<-1>(a, N, batch, s) : launch_col_dir<1>(a, N, batch, s);
 }
 
 hipError_t launch_transpose(const float2* in, float2* out, int R, int C, int batch, hipStream_t s) {

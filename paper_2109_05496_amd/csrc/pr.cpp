@@ -24,7 +24,8 @@ struct PrLayout {
   size_t tw_n, tw_m, H, sy, syc, xh, t1, t2, acc, v, xcur, xprev, z, fgp, part, g, warm, lsp, lsv, total;
 };
 
-int residual_blocks(int m, int n) { return fft_line_blocks(n, m); }
+// Blocks of the residual pass (the second pass of an inverse transform: columns of length n, m of them).
+int residual_blocks(int m, int n) { return fft_second_blocks(n, m); }
 
 PrLayout pr_layout(int D, int m, int n) {
   PrLayout L;
@@ -115,24 +116,25 @@ FftArgs line_args(const float2* in, float2* out, const float2* tw, long long str
 }
 
 // Spectrum (transposed, [n][m]) of a natural-layout [m][n] image: a pass along
-// n, a transpose, a pass along m whose epilogue is `last` (in/out/tw filled here).
+// n, then a column pass along m that writes the transposed layout, with
+// epilogue `last` (in/out/tw filled here).
 ctv_status fft2_to_t(const Ctx& c, const float2* in, float2* out, FftArgs last) {
   float2* t1 = c.at(c.L.t1);
   float2* t2 = c.at(c.L.t2);
   FftArgs a = line_args(in, t1, c.at(c.L.tw_n), c.px);
   CTV_TRY(launch_fft_lines(a, c.n, c.m, -1, 1, c.s), "fft (rows)");
-  CTV_TRY(launch_transpose(t1, t2, c.m, c.n, 1, c.s), "transpose");
-  last.in = t2;
+  last.in = t1;
   last.out = out;
   last.tw = c.at(c.L.tw_m);
   last.in_stride = last.img_stride = c.px;
-  CTV_TRY(launch_fft_lines(last, c.m, c.n, -1, 1, c.s), "fft (columns)");
+  CTV_TRY(launch_fft_second(last, c.m, c.n, -1, 1, t2, c.s), "fft (columns)");
   return CTV_OK;
 }
 
 // Inverse transform of a transposed spectrum [n][m] to natural layout [m][n]:
-// a pass along m (optionally multiplying by Ht on load), a transpose, and a
-// pass along n with epilogue `last` (scale 1/(mn) folded in by the caller).
+// a pass along m (optionally multiplying by Ht on load), then a column pass
+// along n that writes the natural layout, with epilogue `last` (scale 1/(mn)
+// folded in by the caller).
 ctv_status ifft2_from_t(const Ctx& c, const float2* in, const float2* Ht, float2* out, FftArgs last) {
   float2* t1 = c.at(c.L.t1);
   float2* t2 = c.at(c.L.t2);
@@ -142,12 +144,11 @@ ctv_status ifft2_from_t(const Ctx& c, const float2* in, const float2* Ht, float2
     a.H = Ht;
   }
   CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, 1, c.s), "ifft (columns)");
-  CTV_TRY(launch_transpose(t1, t2, c.n, c.m, 1, c.s), "transpose");
-  last.in = t2;
+  last.in = t1;
   last.out = out;
   last.tw = c.at(c.L.tw_n);
   last.in_stride = last.img_stride = c.px;
-  CTV_TRY(launch_fft_lines(last, c.n, c.m, 1, 1, c.s), "ifft (rows)");
+  CTV_TRY(launch_fft_second(last, c.n, c.m, 1, 1, t2, c.s), "ifft (rows)");
   return CTV_OK;
 }
 
@@ -176,15 +177,14 @@ ctv_status accumulate_spectra(const Ctx& c, const float2* r, float2* acc) {
   float2* t1 = c.at(c.L.t1);
   float2* t2 = c.at(c.L.t2);
   CTV_TRY(launch_fft_lines(line_args(r, t1, c.at(c.L.tw_n), c.px), c.n, c.m, -1, c.D, c.s), "fft (rows)");
-  CTV_TRY(launch_transpose(t1, t2, c.m, c.n, c.D, c.s), "transpose");
-  FftArgs q = line_args(t2, nullptr, c.at(c.L.tw_m), c.px);
+  FftArgs q = line_args(t1, nullptr, c.at(c.L.tw_m), c.px);
   q.post = kPostAccumulateAll;
   q.H = c.Ht(0);
   q.H_stride = c.px;
   q.acc = acc;
   q.accumulate = 0;
   q.n_acc = c.D;
-  CTV_TRY(launch_fft_lines(q, c.m, c.n, -1, 1, c.s), "fft (columns, accumulate)");
+  CTV_TRY(launch_fft_second(q, c.m, c.n, -1, 1, t2, c.s), "fft (columns, accumulate)");
   return CTV_OK;
 }
 
@@ -207,14 +207,13 @@ ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, 
   a.H = c.Ht(0);
   a.H_stride = c.px;
   CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, c.D, c.s), "ifft (columns)");
-  CTV_TRY(launch_transpose(t1, t2, c.n, c.m, c.D, c.s), "transpose");
-  FftArgs r = line_args(t2, t2, c.at(c.L.tw_n), c.px);
+  FftArgs r = line_args(t1, t2, c.at(c.L.tw_n), c.px);
   r.post = kPostResidual;
   r.scale = inv;
   r.sy = c.sy(0);
   r.sy_stride = c.px;
   r.partial = part;
-  CTV_TRY(launch_fft_lines(r, c.n, c.m, 1, c.D, c.s), "ifft (rows, residual)");
+  CTV_TRY(launch_fft_second(r, c.n, c.m, 1, c.D, t2, c.s), "ifft (rows, residual)");
   // acc = sum_d conj(H_d) FFT2(residual_d)
   st = accumulate_spectra(c, t2, acc);
   if (st) return st;
@@ -241,14 +240,13 @@ ctv_status data_term(const Ctx& c, const float2* x, double* out) {
   a.H = c.Ht(0);
   a.H_stride = c.px;
   CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, c.D, c.s), "ifft (columns)");
-  CTV_TRY(launch_transpose(t1, t2, c.n, c.m, c.D, c.s), "transpose");
-  FftArgs r = line_args(t2, t2, c.at(c.L.tw_n), c.px);
+  FftArgs r = line_args(t1, t2, c.at(c.L.tw_n), c.px);
   r.post = kPostResidual;
   r.scale = 1.0f / (float)((double)c.m * c.n);
   r.sy = c.sy(0);
   r.sy_stride = c.px;
   r.partial = part;
-  CTV_TRY(launch_fft_lines(r, c.n, c.m, 1, c.D, c.s), "ifft (rows, residual)");
+  CTV_TRY(launch_fft_second(r, c.n, c.m, 1, c.D, t2, c.s), "ifft (rows, residual)");
   CTV_TRY(launch_sum_d(part, c.D * residual_blocks(c.m, c.n), 1, 1, out, c.s), "loss");
   return CTV_OK;
 }
@@ -330,10 +328,9 @@ ctv_status pr_forward(const pr_params* p, int32_t m, int32_t n, const float* x, 
   a.H = c.Ht(0);
   a.H_stride = c.px;
   CTV_TRY(launch_fft_lines(a, m, n, 1, c.D, c.s), "ifft (columns)");
-  CTV_TRY(launch_transpose(c.at(c.L.t1), o, n, m, c.D, c.s), "transpose");
-  FftArgs b = line_args(o, o, c.at(c.L.tw_n), c.px);
+  FftArgs b = line_args(c.at(c.L.t1), o, c.at(c.L.tw_n), c.px);
   b.scale = 1.0f / (float)((double)m * n);
-  CTV_TRY(launch_fft_lines(b, n, m, 1, c.D, c.s), "ifft (rows)");
+  CTV_TRY(launch_fft_second(b, n, m, 1, c.D, o, c.s), "ifft (rows)");
   return CTV_OK;
 }
 
