@@ -87,7 +87,8 @@ typedef struct {
   float alpha;          /* type-II weight in [0, 1] (Eqs. 9-10); ignored for type-I */
   int32_t constraint;   /* CTV_C_* */
   int32_t iters;        /* K >= 0, FGP iterations (Algorithm 2) */
-  int32_t fuse;         /* iterations fused per kernel launch, 1..16; 0 = automatic */
+  int32_t fuse;         /* at most this many iterations fused per kernel launch, 1..16 (a run is
+                           split into the fewest launches, iterations spread evenly); 0 = automatic */
   int32_t tile_waves;   /* tile shape (tuning): 0 = automatic; 4, 8 or 16 wave64s per workgroup in
                            the column-register tile; -1 = the LDS-staged tile (4 waves) */
   int32_t tile_rows;    /* rows per thread: 0 = automatic; column tile 4 or 8 (with waves 4: 8 only);

@@ -148,7 +148,7 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
       const int kstop = (sgi == nseg - 1) ? ke : ke - 1;
       const float* prev = ck;
       for (int k = ks; k < kstop;) {
-        const int Tl = std::min(tl.T, kstop - k);
+        const int Tl = even_split(tl.T, kstop - k);
         float* last = slot(k + Tl - 1 - ks);
         st = fgp_launch(p, tl, cb, m, n, a.b, support, lambda_host + c0, beta, k, Tl, prev, last, nullptr, s,
                         slot(k - ks), (long long)(st_stride / 4));

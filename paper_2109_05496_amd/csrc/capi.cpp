@@ -334,8 +334,8 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
         k += Kc;
       }
     } else do {
-      int Tl = std::min(tl.T, kend - k);
-      if (ckpt_every > 0) Tl = std::min(Tl, (k / ckpt_every + 1) * ckpt_every - k);
+      const int seg_end = ckpt_every > 0 ? std::min(kend, (k / ckpt_every + 1) * ckpt_every) : kend;
+      const int Tl = even_split(tl.T, seg_end - k);
       const bool last = (k + Tl == kend);
       float* dst;
       float* other = (src == bufA + st_off) ? bufB + st_off : bufA + st_off;

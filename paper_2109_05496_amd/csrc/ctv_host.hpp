@@ -24,6 +24,14 @@ Radii make_radii(int kind, float alpha);
 void momentum_table(int method, int kmax, std::vector<float>& beta);
 float step_of(float lam);
 ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out);
+// Iterations for the next launch when `left` iterations remain in a run that
+// takes at most T per launch: the fewest launches, with the iterations spread
+// evenly (8 + 1 becomes 5 + 4; a smaller fusion depth also means a smaller halo).
+inline int even_split(int T, int left) {
+  if (left <= 0) return 0;
+  const int launches = (left + T - 1) / T;
+  return (left + launches - 1) / launches;
+}
 size_t state_bytes(long long batch, long long m, long long n);
 int gap_blocks_per_image(long long px);
 size_t denoise_ws_bytes(int batch, int m, int n);

@@ -400,7 +400,7 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
     int kk = 0;
     const float* src = (warm && have_warm) ? wcur : nullptr;
     do {
-      const int Tl = std::min(tl.T, Kin - kk);
+      const int Tl = even_split(tl.T, Kin - kk);
       const bool last = (kk + Tl == Kin);
       float* dst = last ? (warm ? wnext : nullptr) : (src == fA ? fB : fA);
       ctv_status e = fgp_launch(&p->inner, tl, 1, m, n, reinterpret_cast<const float*>(v), nullptr, &lam, beta, kk,
