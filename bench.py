@@ -12,7 +12,10 @@ record of the dominant kernel (the fused FGP tile kernel; average launch
 duration from HIP events on the stream the kernels run on), and the FP64 CPU
 oracle timed on a bounded sample of the same workload.
 
-The fused kernel performs T = 8 iterations per launch, so its real memory
+Each problem runs in the launch configuration (tile shape, iterations fused
+per launch) the library's autotuner chose for it: from the saved tuning table
+of this GPU model, or tuned live before the warm-up when the table lacks it.
+The fused kernel performs several iterations per launch, so its real memory
 traffic is far below the per-iteration algorithmic bytes: it is bound by VALU
 issue. `roofline` reports the algorithmic arithmetic operations per second
 against the VALU issue peak without packed FP32 (256 CUs x 4 SIMDs x 16 lanes
@@ -21,7 +24,7 @@ sources are unchanged since it was taken), the FP32 FLOP/s against the
 157.3 TFLOP/s vector peak, and, as `hbm_effective`, the algorithmic bytes per
 second against HBM peak that the metric's "%HBM" refers to.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--tuning auto|live|off] [--save-tuning PATH]
 """
 import argparse
 import json
@@ -45,6 +48,8 @@ FLOPS_PER_PX_IT = {"1i": 52, "1a": 52, "2i": 52, "2a": 44}
 OPS_PER_PX_IT = {"1i": 41, "1a": 43, "2i": 45, "2a": 43}
 KIND_INDEX = {"1i": 0, "1a": 1, "2i": 2, "2a": 3}
 PMC_PROFILE = "fgp_col_kernel_2048sq_masked_4kinds_K200_pmc.md"
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TUNING_TABLE = os.path.join(ROOT, "paper_2109_05496_amd", "tuning", "mi355x.jsonl")
 
 
 def parse():
@@ -61,7 +66,42 @@ def parse():
                     help="skip the secondary measurements (batched ragged workload, ...)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 1 GiB device-to-device copies (byte-counter calibration under rocprofv3)")
+    ap.add_argument("--tuning", choices=("auto", "live", "off"), default="auto",
+                    help="launch configuration: auto = the saved tuning table, and the autotuner (untimed, "
+                         "before the warm-up) for problems it does not cover; live = autotune every problem; "
+                         "off = the library default")
+    ap.add_argument("--tuning-table", default=TUNING_TABLE)
+    ap.add_argument("--save-tuning", default=None, help="write the tuning table here at the end")
     return ap.parse_args()
+
+
+class Tuner:
+    """Chooses the launch configuration of each benchmarked problem with the
+    library's autotuner (outside every timed region)."""
+
+    def __init__(self, ctv, mode, table):
+        self.ctv, self.mode, self.table = ctv, mode, None
+        if mode == "auto" and table and os.path.exists(table):
+            ctv.tune_cache_load(table)
+            self.table = os.path.relpath(table, ROOT)
+
+    def plain(self, b, lam, kind, alpha, constraint, support, iters, out=None, workspace=None):
+        if self.mode == "off":
+            return "default"
+        if self.mode == "auto" and self.ctv.tuned(b.shape[-2], b.shape[-1], batch=1 if b.dim() == 2 else b.shape[0],
+                                                  kind=kind, constraint=constraint, iters=iters) is not None:
+            return "table"
+        self.ctv.autotune(b, lam, kind=kind, alpha=alpha, constraint=constraint, support=support, iters=iters,
+                          reps=3, out=out, workspace=workspace)
+        return "live"
+
+    def batched(self, images, b_packed, support_packed=None):
+        if self.mode == "off":
+            return "default"
+        if self.mode == "auto" and self.ctv.batched_tuned(images) is not None:
+            return "table"
+        self.ctv.autotune_batched(images, b_packed, support_packed, reps=2)
+        return "live"
 
 
 def cpu_baseline(c, sample_iters):
@@ -96,7 +136,7 @@ def timed(fn, reps, torch, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def bench_batched(ctv, synth, torch, dev, reps=3):
+def bench_batched(ctv, synth, torch, dev, tuner, reps=3):
     """Ragged batch: 256 images with sides ~ U{128..1024}, per-image lambda and
     kind, 150 iterations, as one HIP-graph launch vs 256 plain calls."""
     imgs = synth.config3(0)
@@ -104,6 +144,11 @@ def bench_batched(ctv, synth, torch, dev, reps=3):
                   iters=d["iters"]) for d in imgs]
     plan = ctv.BatchedPlan(descs)
     bp = plan.pack([d["b"] for d in imgs], device=dev)
+    source = tuner.batched(descs, bp)
+    if source == "live":
+        plan.close()
+        plan = ctv.BatchedPlan(descs)
+    tiling = plan.tiling
     xp = torch.empty_like(bp)
     stream = torch.cuda.current_stream(dev)
     ms_graph = timed(lambda: plan.run(bp, out=xp), reps, torch, stream)
@@ -121,7 +166,7 @@ def bench_batched(ctv, synth, torch, dev, reps=3):
     px_it = sum(d["b"].size * d["iters"] for d in imgs)
     plan.close()
     return {"workload": "256 complex64 images, sides ~ U{128..1024}, lambda log-U[0.01,0.2], kinds 1i/1a, K=150",
-            "px_iters": px_it, "graph_ms": round(ms_graph, 3), "plain_256_calls_ms": round(ms_plain, 3),
+            "tuning": {"fuse": tiling[0], "tile": list(tiling[1:]), "source": source}, "px_iters": px_it, "graph_ms": round(ms_graph, 3), "plain_256_calls_ms": round(ms_plain, 3),
             "speedup": round(ms_plain / ms_graph, 3), "graph_Mpx_it_s": round(px_it / ms_graph / 1e3, 1),
             "plain_Mpx_it_s": round(px_it / ms_plain / 1e3, 1), "bitwise_equal_to_plain": bool(same)}
 
@@ -152,7 +197,7 @@ def bench_adjoint(ctv, synth, torch, dev, reps=3):
             "backward_over_forward": round(ms_b / ms_f, 2)}
 
 
-def bench_pr(ctv, synth, torch, dev, reps=2):
+def bench_pr(ctv, synth, torch, dev, tuner, reps=2):
     """1024^2 object, 4 distances (1.0-2.5 mm, 532 nm, 4 um), Poisson 1000
     photons/pixel; 100 FISTA iterations x 20 FGP iterations (tau 0.01, gamma 1/4).
     The measurements are simulated with the library's own propagator."""
@@ -167,6 +212,10 @@ def bench_pr(ctv, synth, torch, dev, reps=2):
     y = torch.as_tensor(np.stack([synth.poisson_measure(I, P["photons"], rng) for I in inten])).to(dev)
     stream = torch.cuda.current_stream(dev)
     out = {}
+    # the prox is ctv_denoise's problem class (1i, |x| <= 1, batch 1, m x m, K_in)
+    source = tuner.plain(torch.as_tensor(truth.astype(np.complex64)).to(dev), P["tau"] * P["gamma"], "1i", 0.5,
+                         "modulus", None, P["inner"])
+    T, _, tw, tr = ctv.tiling(0, P["inner"], m, m, detail=True)
 
     def run():
         out["x"] = ctv.phase_retrieval(y, P["distances"], P["wavelength"], P["pixel"], tau=P["tau"],
@@ -175,7 +224,7 @@ def bench_pr(ctv, synth, torch, dev, reps=2):
     ms = timed(run, reps, torch, stream)
     fgp_px_it = m * m * P["outer"] * P["inner"]
     return {"workload": "1024^2, D=4, 100 outer x 20 FGP iterations, type-1i, |x|<=1",
-            "ms": round(ms, 3), "ms_per_outer_iteration": round(ms / P["outer"], 4),
+            "prox_tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "ms": round(ms, 3), "ms_per_outer_iteration": round(ms / P["outer"], 4),
             "fgp_Mpx_it_s_equiv": round(fgp_px_it / ms / 1e3, 1), "fft2_per_outer_iteration": 2 * len(P["distances"]) + 2}
 
 
@@ -198,7 +247,7 @@ def median_ms(fn, reps, torch, stream, before=None):
     return times[len(times) // 2]
 
 
-def bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, reps=5):
+def bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, tuner, reps=5):
     """The same masked 2048^2 workload (four kinds x 200 iterations) submitted
     as one ragged batched plan (one HIP graph) instead of four plain calls:
     four times the tiles per fused step fill the 512 resident workgroups
@@ -211,6 +260,11 @@ def bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, reps=5):
     plan = ctv.BatchedPlan(descs)
     bp = plan.pack([c["b"]] * len(kinds), device=dev)
     sp = plan.pack_support([c["mask"]] * len(kinds), device=dev)
+    source = tuner.batched(descs, bp, sp)
+    if source == "live":
+        plan.close()
+        plan = ctv.BatchedPlan(descs)
+    tiling = plan.tiling
     xp = torch.empty_like(bp)
     stream = torch.cuda.current_stream(dev)
     ms = timed(lambda: plan.run(bp, sp, out=xp), reps, torch, stream)
@@ -219,23 +273,26 @@ def bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, reps=5):
     plan.close()
     px_it = len(kinds) * m * n * c["iters"]
     return {"workload": f"masked {m}x{n}, four kinds x {c['iters']} iterations as one batched plan",
-            "ms": round(ms, 3), "Mpx_it_s": round(px_it / ms / 1e3, 1), "bitwise_equal_to_plain": bool(same)}
+            "tuning": {"fuse": tiling[0], "tile": list(tiling[1:]), "source": source}, "ms": round(ms, 3), "Mpx_it_s": round(px_it / ms / 1e3, 1), "bitwise_equal_to_plain": bool(same)}
 
 
-def bench_small(ctv, synth, torch, dev, reps=20):
+def bench_small(ctv, synth, torch, dev, tuner, reps=20):
     """64 x 64, type-1i, lambda 0.05, K = 100: latency of one solve."""
     c = synth.config1(0)
     b = torch.as_tensor(c["b"]).to(dev)
     x = torch.empty_like(b)
     ws = torch.empty(ctv.workspace_size(64, 64, 1, iters=c["iters"])[0], dtype=torch.uint8, device=dev)
+    source = tuner.plain(b, c["lam"], "1i", 0.5, "modulus", None, c["iters"], out=x, workspace=ws)
+    T, _, tw, tr = ctv.tiling(0, c["iters"], 64, 64, detail=True)
     stream = torch.cuda.current_stream(dev)
     ms = median_ms(lambda: ctv.denoise(b, c["lam"], kind="1i", iters=c["iters"], out=x, workspace=ws),
                    reps, torch, stream)
-    return {"workload": "64x64 complex64, type-1i, lambda 0.05, K=100, |x|<=1", "us_per_solve": round(ms * 1e3, 1),
+    return {"workload": "64x64 complex64, type-1i, lambda 0.05, K=100, |x|<=1",
+            "tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "us_per_solve": round(ms * 1e3, 1),
             "Mpx_it_s": round(64 * 64 * c["iters"] / ms / 1e3, 1)}
 
 
-def bench_out_of_cache(ctv, synth, torch, dev, size=8192, iters=48, reps=7):
+def bench_out_of_cache(ctv, synth, torch, dev, tuner, size=8192, iters=48, reps=7):
     """The masked configuration at 8192^2 (about 5.4 GB resident: b, x, two
     dual-state buffers, mask), type-1i: warm median, and median with a 512 MB
     write ahead of every repetition so the 256 MB Infinity Cache holds none of
@@ -247,6 +304,8 @@ def bench_out_of_cache(ctv, synth, torch, dev, size=8192, iters=48, reps=7):
     ws = torch.empty(ctv.workspace_size(size, size, 1, iters=iters)[0], dtype=torch.uint8, device=dev)
     flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
+    source = tuner.plain(b, c["lam"], "1i", c["alpha"], "modulus", mask, iters, out=x, workspace=ws)
+    T, _, tw, tr = ctv.tiling(0, iters, size, size, detail=True)
 
     def run():
         ctv.denoise(b, c["lam"], kind="1i", support=mask, iters=iters, out=x, workspace=ws)
@@ -254,7 +313,8 @@ def bench_out_of_cache(ctv, synth, torch, dev, size=8192, iters=48, reps=7):
     warm = median_ms(run, reps, torch, stream)
     cold = median_ms(run, reps, torch, stream, before=lambda: flush.fill_(1.0))
     px_it = size * size * iters
-    return {"workload": f"masked {size}x{size} complex64, type-1i, K={iters}", "warm_ms": round(warm, 3),
+    return {"workload": f"masked {size}x{size} complex64, type-1i, K={iters}",
+            "tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "warm_ms": round(warm, 3),
             "cold_ms": round(cold, 3), "warm_Mpx_it_s": round(px_it / warm / 1e3, 1),
             "cold_Mpx_it_s": round(px_it / cold / 1e3, 1),
             "cold_hbm_effective_frac": round(px_it * BYTES_PER_PX_IT_MASKED / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
@@ -288,6 +348,14 @@ def main():
         ctv.denoise(b, c["lam"], kind=kind, alpha=c["alpha"], constraint=c["constraint"], support=mask,
                     iters=K, fuse=args.fuse, out=x, workspace=ws)
 
+    from paper_2109_05496_amd import prof_summary, tiling
+    tuner = Tuner(ctv, "off" if args.fuse else args.tuning, args.tuning_table)
+    by_kind = {}
+    for kind in kinds:
+        source = tuner.plain(b, c["lam"], kind, c["alpha"], c["constraint"], mask, K, out=x, workspace=ws)
+        T_k, _, tw_k, tr_k = tiling(args.fuse, K, m, n, detail=True, kind=kind, constraint=c["constraint"])
+        by_kind[kind] = {"fuse": T_k, "tile": [tw_k, tr_k], "source": source}
+
     for _ in range(args.warmup):
         for kind in kinds:
             run_kind(kind)
@@ -315,10 +383,9 @@ def main():
     # Roofline of the dominant kernel: the fused tile kernel (one instantiation
     # per TV kind; every launch in the timed region is one of them, so the
     # average launch duration is the kind's event time over its launch count).
-    from paper_2109_05496_amd import prof_summary, tiling
-    T, rh, tw, tr = tiling(args.fuse, K, m, n, detail=True)
-    launches = math.ceil(K / T)
     dom = max(kinds, key=lambda k: per_kind_ms[k])
+    T, (tw, tr) = by_kind[dom]["fuse"], by_kind[dom]["tile"]
+    launches = math.ceil(K / T)
     kname = f"void ctv::fgp_col_kernel<{KIND_INDEX[dom]}, 1, true, {tw}, {tr}, false>(ctv::FgpPlainArgs)"
     avg_launch_s = per_kind_ms[dom] / args.steps / launches * 1e-3
     alg_bytes_launch = BYTES_PER_PX_IT_MASKED * m * n * K / launches
@@ -328,7 +395,9 @@ def main():
     achieved_tflops = alg_flops_launch / avg_launch_s / 1e12
     achieved_gops = alg_ops_launch / avg_launch_s / 1e9
     pmc = prof_summary.load_pmc(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", PMC_PROFILE))
-    kp = pmc["kernels"].get(kname) if (pmc and args.size == 2048 and K == 200 and args.fuse == 0) else None
+    # the profile counts only while it was taken with the same launch configuration
+    same_config = bool(pmc) and pmc.get("tuning") == prof_summary.tuning_signature(by_kind)
+    kp = pmc["kernels"].get(kname) if (same_config and args.size == 2048 and K == 200 and args.fuse == 0) else None
     roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": round(VALU_OPS_PEAK_GOPS, 1),
             "unit": "Gop/s", "frac": round(achieved_gops / VALU_OPS_PEAK_GOPS, 4),
             "traffic": kp["traffic_bytes"] if kp else None,
@@ -349,8 +418,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"masked {m}x{n} complex64 CTV denoise, all four TV kinds x {K} FGP iterations",
                       "size": [m, n], "kinds": kinds, "iters": K, "lambda": c["lam"], "alpha": c["alpha"],
-                      "constraint": "|x|<=1 + 70% square support", "fuse": T, "region_rows": rh,
-                      "tile": [tw, tr]},
+                      "constraint": "|x|<=1 + 70% square support"},
+           "tuning": {"mode": tuner.mode, "table": tuner.table, "by_kind": by_kind},
            "per_kind_ms": {k: round(v / args.steps, 3) for k, v in per_kind_ms.items()},
            "wall_s": round(wall, 3),
            "roofline": roof}
@@ -360,12 +429,12 @@ def main():
             for kind in kinds:
                 run_kind(kind)
                 x_plain[kind] = x.clone()
-            out["four_kinds_one_plan"] = bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain)
-        out["small_64"] = bench_small(ctv, synth, torch, dev)
-        out["out_of_cache_8192"] = bench_out_of_cache(ctv, synth, torch, dev)
-        out["batched"] = bench_batched(ctv, synth, torch, dev)
+            out["four_kinds_one_plan"] = bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, tuner)
+        out["small_64"] = bench_small(ctv, synth, torch, dev, tuner)
+        out["out_of_cache_8192"] = bench_out_of_cache(ctv, synth, torch, dev, tuner)
+        out["batched"] = bench_batched(ctv, synth, torch, dev, tuner)
         out["adjoint"] = bench_adjoint(ctv, synth, torch, dev)
-        out["phase_retrieval"] = bench_pr(ctv, synth, torch, dev)
+        out["phase_retrieval"] = bench_pr(ctv, synth, torch, dev, tuner)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -373,6 +442,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes_each_way"] = src.numel() * 4
+    if args.save_tuning:
+        ctv.tune_cache_save(args.save_tuning)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample_iters)
     print(json.dumps(out), flush=True)

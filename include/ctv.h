@@ -182,6 +182,75 @@ ctv_status ctv_denoise_batched(ctv_batched_plan* plan, const float* b_packed,
                                const uint8_t* support_packed, float* x_packed, void* ws,
                                size_t ws_bytes, ctv_stream_t stream);
 ctv_status ctv_batched_plan_destroy(ctv_batched_plan* plan);
+/* Launch configuration the plan was built with (iterations fused per launch,
+ * tile_waves, tile_rows); any output pointer may be NULL. */
+ctv_status ctv_batched_plan_tiling(const ctv_batched_plan* plan, int32_t* fuse_out,
+                                   int32_t* tile_waves_out, int32_t* tile_rows_out);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning of the fused forward kernel's launch configuration: the tile
+ * shape and the number of FGP iterations fused per launch (the tiling and
+ * temporal fusion of the iteration loop of Algorithm 2; the paper runs it
+ * unfused). Every configuration computes the same iterates bit for bit, so a
+ * tuning choice changes only the speed.
+ *
+ * ctv_autotune runs ctv_denoise on the caller's problem (same arguments as a
+ * plain call without gap, state or checkpoints) once per candidate (tile
+ * shape, fuse) pair, times `reps` further calls of each on `stream` with HIP
+ * events (median), and records the fastest in a process-wide table keyed by
+ * the device's architecture and CU count and by (tv_kind, constraint, method,
+ * batch, m, n, iters); the support mask is not part of the key. ctv_denoise,
+ * ctv_tiling and pr_prox_grad (its inner prox) use a recorded entry whenever
+ * params.fuse, tile_waves and tile_rows are all 0 (and schedule is not
+ * CTV_S_FLOW); ctv_denoise_backward always uses the default.
+ * ctv_batched_autotune does the same for a batched plan: it builds, runs and
+ * destroys one plan per candidate and records the fastest under a key derived
+ * from (constraint, method, and per image m, n, effective K, tv_kind, has
+ * support); ctv_batched_plan_create with fuse and tile 0 then uses it. Its
+ * ws must hold ctv_batched_workspace_size() bytes of a plan of these images
+ * (the same for every configuration).
+ *   reps         1..100 timed calls per candidate.
+ *   results      host array of max_results entries (may be NULL with
+ *                max_results = 0): every candidate timed, in the order tried.
+ *   num_results  host: number of candidates timed (may be NULL).
+ *   best         host: the recorded configuration (may be NULL).
+ * x (x_packed) holds the solution afterwards: every candidate computes it.
+ * Both calls block the host (they synchronize on their events), allocate
+ * nothing in ctv_autotune (ctv_batched_autotune allocates and frees each
+ * candidate's plan tables) and fail with CTV_ERR_INVALID_ARG while `stream`
+ * is being captured. The table is shared by all threads (guarded by a lock).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t fuse;        /* at most this many iterations fused per launch */
+  int32_t tile_waves;  /* wave64s per workgroup */
+  int32_t tile_rows;   /* rows per thread */
+  float ms;            /* median time of one call, milliseconds */
+} ctv_tuning;
+
+ctv_status ctv_autotune(const ctv_params* p, int32_t batch, int32_t m, int32_t n, const float* b,
+                        const float* lambda_host, const uint8_t* support, float* x, void* ws,
+                        size_t ws_bytes, int32_t reps, ctv_tuning* results, int32_t max_results,
+                        int32_t* num_results, ctv_tuning* best, ctv_stream_t stream);
+ctv_status ctv_batched_autotune(const ctv_image_desc* descs_host, int32_t count, const ctv_params* common,
+                                const float* b_packed, const uint8_t* support_packed, float* x_packed,
+                                void* ws, size_t ws_bytes, int32_t reps, ctv_tuning* results, int32_t max_results,
+                                int32_t* num_results, ctv_tuning* best, ctv_stream_t stream);
+/* Whether the table holds an entry for this plain problem on the current
+ * device (*found = 1, *entry = the entry) or not (*found = 0). entry may be NULL. */
+ctv_status ctv_tune_lookup(const ctv_params* p, int32_t batch, int32_t m, int32_t n, int32_t* found,
+                           ctv_tuning* entry);
+/* The same for a batched plan of these images (the key of ctv_batched_autotune). */
+ctv_status ctv_batched_tune_lookup(const ctv_image_desc* descs_host, int32_t count, const ctv_params* common,
+                                   int32_t* found, ctv_tuning* entry);
+/* The tuning table as text, one JSON object per line ("arch", "key", "fuse",
+ * "tile_waves", "tile_rows", "ms", "what"). Loading merges the file's entries
+ * into the table (an entry with the same arch and key is replaced); a
+ * malformed line fails with CTV_ERR_INVALID_ARG and merges nothing. Entries of
+ * other architectures are kept and saved again but never used. */
+ctv_status ctv_tune_cache_save(const char* path);
+ctv_status ctv_tune_cache_load(const char* path);
+ctv_status ctv_tune_cache_clear(void);
+int32_t ctv_tune_cache_size(void);
 
 /* ---------------------------------------------------------------------------
  * ctv_denoise_backward - exact reverse-mode derivative of the K-step map

@@ -52,6 +52,10 @@ class PrParams(ctypes.Structure):
                 ("warm_start", c_i32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("fuse", c_i32), ("tile_waves", c_i32), ("tile_rows", c_i32), ("ms", c_f)]
+
+
 _SIGS = {
     "ctv_version": (c_i32, []),
     "ctv_last_error": (ctypes.c_char_p, []),
@@ -65,6 +69,21 @@ _SIGS = {
     "ctv_batched_workspace_size": (c_i32, [c_vp, c_psz]),
     "ctv_denoise_batched": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "ctv_batched_plan_destroy": (c_i32, [c_vp]),
+    "ctv_batched_plan_tiling": (c_i32, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
+    "ctv_autotune": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_f), c_vp, c_vp,
+                             c_vp, c_sz, c_i32, ctypes.POINTER(Tuning), c_i32, ctypes.POINTER(c_i32),
+                             ctypes.POINTER(Tuning), c_vp]),
+    "ctv_batched_autotune": (c_i32, [ctypes.POINTER(ImageDesc), c_i32, ctypes.POINTER(Params), c_vp, c_vp, c_vp,
+                                     c_vp, c_sz, c_i32, ctypes.POINTER(Tuning), c_i32, ctypes.POINTER(c_i32),
+                                     ctypes.POINTER(Tuning), c_vp]),
+    "ctv_tune_lookup": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, ctypes.POINTER(c_i32),
+                                ctypes.POINTER(Tuning)]),
+    "ctv_batched_tune_lookup": (c_i32, [ctypes.POINTER(ImageDesc), c_i32, ctypes.POINTER(Params),
+                                        ctypes.POINTER(c_i32), ctypes.POINTER(Tuning)]),
+    "ctv_tune_cache_save": (c_i32, [ctypes.c_char_p]),
+    "ctv_tune_cache_load": (c_i32, [ctypes.c_char_p]),
+    "ctv_tune_cache_clear": (c_i32, []),
+    "ctv_tune_cache_size": (c_i32, []),
     "ctv_backward_workspace_size": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_i32, c_psz]),
     "ctv_denoise_backward": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_f),
                                      c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),

@@ -38,10 +38,11 @@ def _lams(lam, batch):
     return (ctypes.c_float * batch)(*lam)
 
 
-def tiling(fuse=0, iters=100, m=2048, n=2048, batch=1, tile=(0, 0), detail=False):
+def tiling(fuse=0, iters=100, m=2048, n=2048, batch=1, tile=(0, 0), detail=False, kind="1i",
+           constraint="modulus", method="fgp"):
     """(iterations fused per launch, tile region rows) that ctv_denoise uses;
     with detail=True also (tile_waves, rows_per_thread)."""
-    p = make_params("1i", 0.5, "modulus", iters, fuse, tile)
+    p = make_params(kind, 0.5, constraint, iters, fuse, tile, method)
     t, r, w, rp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     call("ctv_tiling", ctypes.byref(p), batch, m, n, ctypes.byref(t), ctypes.byref(r), ctypes.byref(w),
          ctypes.byref(rp))
@@ -160,6 +161,129 @@ class CTVDenoise(torch.autograd.Function):
         return gb, glam, None, None, None, None, None, None, None, None
 
 
+def _image_descs(images):
+    """ctv_image_desc array for images packed back to back in the order given,
+    with (offsets, support offsets, shapes, total pixels, support bytes)."""
+    descs = (_lib.ImageDesc * len(images))()
+    off = 0
+    soff = 0
+    offsets, support_offsets, shapes = [], [], []
+    for d, im in zip(descs, images):
+        m, n = int(im["m"]), int(im["n"])
+        d.offset = off
+        d.m, d.n = m, n
+        d.lam = float(im["lam"])
+        d.tv_kind = _lib.KINDS[im.get("kind", "1i")]
+        d.alpha = float(im.get("alpha", 0.5))
+        d.iters = int(im.get("iters", 100))
+        if im.get("has_support"):
+            d.support_offset = soff
+            support_offsets.append(soff)
+            soff += m * n
+        else:
+            d.support_offset = -1
+            support_offsets.append(-1)
+        offsets.append(off)
+        shapes.append((m, n))
+        off += m * n
+    return descs, offsets, support_offsets, shapes, off, soff
+
+
+def _tunings(arr, count):
+    return [dict(fuse=arr[i].fuse, tile=(arr[i].tile_waves, arr[i].tile_rows), ms=arr[i].ms) for i in range(count)]
+
+
+_MAX_CANDIDATES = 64
+
+
+def autotune(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, iters=100, method="fgp", reps=3,
+             out=None, workspace=None):
+    """Times every candidate (tile shape, fuse) for this problem with
+    ctv_autotune and records the fastest for the process; later automatic
+    calls of ``denoise`` (and ``tiling``, and the prox of ``phase_retrieval``)
+    with the same kind, constraint, method, batch, size and iters use it.
+    Returns {"best": {...}, "candidates": [...]}; ``out`` (if given) holds the
+    solution afterwards."""
+    _require_cuda(b, "b", torch.complex64)
+    bb = b.unsqueeze(0) if b.dim() == 2 else b
+    B, m, n = bb.shape
+    dev = bb.device
+    p = make_params(kind, alpha, constraint, iters, 0, method=method)
+    if support is not None:
+        _require_cuda(support, "support", torch.uint8)
+    x = out if out is not None else torch.empty_like(bb)
+    _require_cuda(x, "out", torch.complex64)
+    ws_bytes, _ = workspace_size(m, n, B, kind, alpha, constraint, iters, 0, 0, method)
+    ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    res = (_lib.Tuning * _MAX_CANDIDATES)()
+    cnt = ctypes.c_int32()
+    best = _lib.Tuning()
+    call("ctv_autotune", ctypes.byref(p), B, m, n, _ptr(bb), _lams(lam, B), _ptr(support), _ptr(x), _ptr(ws),
+         ws.numel(), int(reps), res, _MAX_CANDIDATES, ctypes.byref(cnt), ctypes.byref(best), _stream(dev))
+    return {"best": _tunings([best], 1)[0], "candidates": _tunings(res, min(cnt.value, _MAX_CANDIDATES))}
+
+
+def autotune_batched(images, b_packed, support_packed=None, constraint="modulus", method="fgp", reps=3, out=None):
+    """ctv_batched_autotune for a ragged batch (``images`` as for BatchedPlan,
+    ``b_packed`` packed in the same order): a BatchedPlan of these images
+    created afterwards with fuse 0 uses the fastest configuration."""
+    _require_cuda(b_packed, "b_packed", torch.complex64)
+    dev = b_packed.device
+    descs = _image_descs(images)[0]
+    common = make_params("1i", 0.5, constraint, 0, 0, method=method)
+    x = out if out is not None else torch.empty_like(b_packed)
+    sizing = BatchedPlan(images, constraint, fuse=8, method=method)  # workspace size only
+    ws_bytes = sizing.ws_bytes
+    sizing.close()
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    res = (_lib.Tuning * _MAX_CANDIDATES)()
+    cnt = ctypes.c_int32()
+    best = _lib.Tuning()
+    call("ctv_batched_autotune", descs, len(images), ctypes.byref(common), _ptr(b_packed), _ptr(support_packed),
+         _ptr(x), _ptr(ws), ws.numel(), int(reps), res, _MAX_CANDIDATES, ctypes.byref(cnt), ctypes.byref(best),
+         _stream(dev))
+    return {"best": _tunings([best], 1)[0], "candidates": _tunings(res, min(cnt.value, _MAX_CANDIDATES))}
+
+
+def tuned(m, n, batch=1, kind="1i", alpha=0.5, constraint="modulus", iters=100, method="fgp"):
+    """The recorded configuration {"fuse", "tile"} for this plain problem on
+    the current device, or None."""
+    p = make_params(kind, alpha, constraint, iters, 0, method=method)
+    found = ctypes.c_int32()
+    e = _lib.Tuning()
+    call("ctv_tune_lookup", ctypes.byref(p), batch, m, n, ctypes.byref(found), ctypes.byref(e))
+    return dict(fuse=e.fuse, tile=(e.tile_waves, e.tile_rows)) if found.value else None
+
+
+def batched_tuned(images, constraint="modulus", method="fgp"):
+    """The recorded configuration {"fuse", "tile"} for a batched plan of these
+    images on the current device, or None."""
+    descs = _image_descs(images)[0]
+    common = make_params("1i", 0.5, constraint, 0, 0, method=method)
+    found = ctypes.c_int32()
+    e = _lib.Tuning()
+    call("ctv_batched_tune_lookup", descs, len(images), ctypes.byref(common), ctypes.byref(found), ctypes.byref(e))
+    return dict(fuse=e.fuse, tile=(e.tile_waves, e.tile_rows)) if found.value else None
+
+
+def tune_cache_save(path):
+    """Writes the tuning table (one JSON object per line)."""
+    call("ctv_tune_cache_save", str(path).encode())
+
+
+def tune_cache_load(path):
+    """Merges a saved tuning table into the process's table."""
+    call("ctv_tune_cache_load", str(path).encode())
+
+
+def tune_cache_clear():
+    call("ctv_tune_cache_clear")
+
+
+def tune_cache_size():
+    return int(_lib.lib().ctv_tune_cache_size())
+
+
 class BatchedPlan:
     """Ragged batch of images denoised in one HIP-graph launch.
 
@@ -168,32 +292,10 @@ class BatchedPlan:
     order given; ``offsets`` gives each image's first pixel.
     """
 
-    def __init__(self, images, constraint="modulus", fuse=0, method="fgp"):
-        descs = (_lib.ImageDesc * len(images))()
-        off = 0
-        soff = 0
-        self.offsets, self.support_offsets, self.shapes = [], [], []
-        for d, im in zip(descs, images):
-            m, n = int(im["m"]), int(im["n"])
-            d.offset = off
-            d.m, d.n = m, n
-            d.lam = float(im["lam"])
-            d.tv_kind = _lib.KINDS[im.get("kind", "1i")]
-            d.alpha = float(im.get("alpha", 0.5))
-            d.iters = int(im.get("iters", 100))
-            if im.get("has_support"):
-                d.support_offset = soff
-                self.support_offsets.append(soff)
-                soff += m * n
-            else:
-                d.support_offset = -1
-                self.support_offsets.append(-1)
-            self.offsets.append(off)
-            self.shapes.append((m, n))
-            off += m * n
-        self.total_pixels = off
-        self.support_bytes = soff
-        common = make_params("1i", 0.5, constraint, 0, fuse, method=method)
+    def __init__(self, images, constraint="modulus", fuse=0, method="fgp", tile=(0, 0)):
+        descs, self.offsets, self.support_offsets, self.shapes, self.total_pixels, self.support_bytes = \
+            _image_descs(images)
+        common = make_params("1i", 0.5, constraint, 0, fuse, tile, method=method)
         h = ctypes.c_void_p()
         call("ctv_batched_plan_create", descs, len(images), ctypes.byref(common), ctypes.byref(h))
         self._h = h
@@ -201,6 +303,13 @@ class BatchedPlan:
         call("ctv_batched_workspace_size", self._h, ctypes.byref(ws))
         self.ws_bytes = ws.value
         self._ws = None
+
+    @property
+    def tiling(self):
+        """(iterations fused per launch, tile_waves, tile_rows) of the plan."""
+        f, w, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        call("ctv_batched_plan_tiling", self._h, ctypes.byref(f), ctypes.byref(w), ctypes.byref(r))
+        return f.value, w.value, r.value
 
     def pack(self, imgs, device="cuda"):
         flat = torch.empty(self.total_pixels, dtype=torch.complex64, device=device)

@@ -153,6 +153,14 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
   tp.iters = std::max(kmax, 1);
   st = choose_tiling(&tp, 1, 1, count, &tl);
   if (st) return st;
+  if (common->fuse == 0 && common->tile_waves == 0 && common->tile_rows == 0) {
+    Tiling tuned;
+    if (tuned_lookup(batched_tune_key(descs, count, common), &tuned) &&
+        fgp_batched_kernel_ptr(common->constraint, tuned.shape)) {
+      clamp_fuse(&tuned, tp.iters);
+      tl = tuned;
+    }
+  }
   ctv_batched_plan* p = new ctv_batched_plan();
   p->count = count;
   p->constraint = common->constraint;
@@ -245,6 +253,15 @@ ctv_status ctv_denoise_batched(ctv_batched_plan* p, const float* b, const uint8_
   }
   hipError_t e = hipGraphLaunch(p->exec, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return CTV_OK;
+}
+
+ctv_status ctv_batched_plan_tiling(const ctv_batched_plan* p, int32_t* fuse_out, int32_t* tile_waves_out,
+                                   int32_t* tile_rows_out) {
+  if (!p) return fail(CTV_ERR_INVALID_ARG, "plan is NULL");
+  if (fuse_out) *fuse_out = p->tiling.T;
+  if (tile_waves_out) *tile_waves_out = p->tiling.shape.waves;
+  if (tile_rows_out) *tile_rows_out = p->tiling.shape.rows_per_thread;
   return CTV_OK;
 }
 

@@ -87,28 +87,33 @@ bool valid_tile_shape(const TileShape& ts) {
   return ts.rows_per_thread == 4 || ts.rows_per_thread == 8 || ts.rows_per_thread == 16;
 }
 
-ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out) {
-  (void)m;
-  (void)n;
-  (void)batch;
+void clamp_fuse(Tiling* t, int iters) {
+  // halo H <= (min(64, rows) - 1) / 2 keeps at least one output row and column;
+  // the epilogue launch needs H = T + 1.
+  const int hmax = (std::min(64, t->shape.rows()) - 1) / 2;
+  t->T = std::min(t->T, hmax - 1);
+  if (iters > 0) t->T = std::min(t->T, iters);
+  t->T = std::max(t->T, 1);
+}
+
+ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out, bool use_tuned) {
   Tiling t;
   t.shape.waves = 8;
   t.shape.rows_per_thread = 8;
+  // Default from the tiling sweep on MI355X (2048^2, K = 200): 8 waves x 8 rows
+  // (64 x 64 regions) with 8 fused iterations.
+  t.T = 8;
   if (p->tile_waves != 0 || p->tile_rows != 0) {
     if (p->tile_waves == 0 || p->tile_rows == 0) return fail(CTV_ERR_INVALID_ARG, "tile_waves and tile_rows must be set together");
     t.shape.waves = p->tile_waves < 0 ? 0 : p->tile_waves;
     t.shape.rows_per_thread = p->tile_rows;
     if (p->tile_waves < -1 || !valid_tile_shape(t.shape)) return fail(CTV_ERR_INVALID_ARG, "unsupported tile shape");
+  } else if (use_tuned && p->fuse == 0) {
+    Tiling tuned;
+    if (tuned_lookup(plain_tune_key(p, batch, m, n), &tuned) && valid_tile_shape(tuned.shape)) t = tuned;
   }
-  // halo H <= (min(64, rows) - 1) / 2 keeps at least one output row and column;
-  // the epilogue launch needs H = T + 1.
-  const int hmax = (std::min(64, t.shape.rows()) - 1) / 2;
-  // Default from the tiling sweep on MI355X (2048^2, K = 200): 8 waves x 8 rows
-  // (64 x 64 regions) with 8 fused iterations.
-  t.T = p->fuse > 0 ? p->fuse : 8;
-  t.T = std::min(t.T, hmax - 1);
-  if (p->iters > 0) t.T = std::min(t.T, p->iters);
-  t.T = std::max(t.T, 1);
+  if (p->fuse > 0) t.T = p->fuse;
+  clamp_fuse(&t, p->iters);
   *out = t;
   return CTV_OK;
 }
@@ -196,7 +201,7 @@ ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, 
   if (st) return st;
   if (batch < 1 || m < 1 || n < 1) return fail(CTV_ERR_INVALID_ARG, "batch, m and n must be >= 1");
   Tiling t;
-  st = choose_tiling(p, m, n, batch, &t);
+  st = choose_tiling(p, m, n, batch, &t, p->schedule != CTV_S_FLOW);
   if (st) return st;
   if (fuse_out) *fuse_out = t.T;
   if (region_rows_out) *region_rows_out = t.shape.rows();
@@ -240,7 +245,7 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
   int* flow_mem = reinterpret_cast<int*>(
       wsb + 2 * align_up(st_full) + align_up((size_t)batch * gap_blocks_per_image(px) * sizeof(double)));
   Tiling tl;
-  st = choose_tiling(p, m, n, batch, &tl);
+  st = choose_tiling(p, m, n, batch, &tl, p->schedule != CTV_S_FLOW);
   if (st) return st;
   const bool flow_ok = ckpt_every == 0 && p->iters > 0 && tl.shape.waves == 8 && tl.shape.rows_per_thread == 8;
   if (p->schedule == CTV_S_FLOW && !flow_ok)

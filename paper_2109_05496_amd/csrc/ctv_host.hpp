@@ -23,7 +23,15 @@ ctv_status validate_lambda(float lam);
 Radii make_radii(int kind, float alpha);
 void momentum_table(int method, int kmax, std::vector<float>& beta);
 float step_of(float lam);
-ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out);
+// Launch configuration for a plain call: the explicit fuse / tile of p, else
+// (use_tuned) an entry recorded by ctv_autotune for this problem, else the default.
+ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* out, bool use_tuned = false);
+// Limits the fusion depth to what the tile shape's halo and the run allow.
+void clamp_fuse(Tiling* t, int iters);
+// Tuning table (autotune.cpp): problem keys and lookup for the current device.
+uint64_t plain_tune_key(const ctv_params* p, int batch, int m, int n);
+uint64_t batched_tune_key(const ctv_image_desc* d, int count, const ctv_params* common);
+bool tuned_lookup(uint64_t key, Tiling* out);
 // Iterations for the next launch when `left` iterations remain in a run that
 // takes at most T per launch: the fewest launches, with the iterations spread
 // evenly (8 + 1 becomes 5 + 4; a smaller fusion depth also means a smaller halo).

@@ -379,7 +379,7 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   CTV_TRY(launch_copy_c(xcur, z, c.px, c.s), "copy");
   float gamma = p->gamma > 0.0f ? p->gamma : 1.0f / (float)c.D;
   Tiling tl;
-  st = choose_tiling(&p->inner, m, n, 1, &tl);
+  st = choose_tiling(&p->inner, m, n, 1, &tl, p->inner.schedule != CTV_S_FLOW);
   if (st) return st;
   const int Kin = p->inner.iters;
   std::vector<float> beta;

@@ -6,8 +6,9 @@
 The PMC summary carries a JSON block (per-dispatch FETCH_SIZE / WRITE_SIZE of
 the FGP tile kernel, scaled by the factors the same counters read for a 1 GiB
 device-to-device copy, and the VALU issue utilisation) together with the
-SHA-256 of the kernel sources it was measured on; bench.py uses those numbers
-only while the sources still hash the same.
+SHA-256 of the kernel sources it was measured on and the launch configuration
+(fusion depth and tile shape per TV kind) of the profiled runs; bench.py uses
+those numbers only while both still match.
 """
 import argparse
 import collections
@@ -63,7 +64,21 @@ def stats(csv_path, out, cmd, match=None, title=None):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
-def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, kernel_prefix="void ctv::fgp_col_kernel"):
+def tuning_signature(by_kind):
+    """{kind: [fuse, tile_waves, tile_rows]} of a benchmark's launch configuration."""
+    return {k: [int(v["fuse"])] + [int(t) for t in v["tile"]] for k, v in sorted(by_kind.items())}
+
+
+def bench_tuning(log_path):
+    """Launch configuration recorded in the JSON line a bench.py run printed."""
+    for line in reversed(open(log_path).read().splitlines()):
+        if line.startswith("{"):
+            return tuning_signature(json.loads(line)["tuning"]["by_kind"])
+    raise ValueError(f"no bench.py result line in {log_path}")
+
+
+def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, kernel_prefix="void ctv::fgp_col_kernel",
+        bench_log=None):
     fetch, write, valu = _counters(fetch_dir), _counters(write_dir), _counters(valu_dir)
     copy = next(k for k in fetch if "copyBuffer" in k)
     f_factor = copy_bytes / 1024.0 / _largest(fetch[copy]["FETCH_SIZE"])
@@ -86,7 +101,7 @@ def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, kernel_pre
                          "valu_insts_per_dispatch": round(_mean(v["SQ_INSTS_VALU"])) if v else None}
     doc = {"source_sha256": kernel_source_hash(), "fetch_factor": round(f_factor, 4),
            "write_factor": round(w_factor, 4), "calibration": f"{copy} of {copy_bytes} bytes",
-           "kernels": per_kernel}
+           "tuning": bench_tuning(bench_log) if bench_log else None, "kernels": per_kernel}
     lines = ["# rocprofv3 PMC summary", "", f"Command (one run per counter group): `{cmd}`", "",
              "Byte counters are per dispatch, scaled by the factor the same counter reads for a "
              f"{copy_bytes >> 30} GiB device-to-device copy in the same process "
@@ -127,8 +142,10 @@ if __name__ == "__main__":
     p.add_argument("valu")
     p.add_argument("out")
     p.add_argument("--cmd", required=True)
+    p.add_argument("--bench-log", default=None, help="output of one of the profiled bench.py runs "
+                                                      "(records the launch configuration it used)")
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.csv, a.out, a.cmd, a.match, a.title)
     else:
-        pmc(a.fetch, a.write, a.valu, a.out, a.cmd)
+        pmc(a.fetch, a.write, a.valu, a.out, a.cmd, bench_log=a.bench_log)
