@@ -17,9 +17,13 @@
  *   - Images are complex64, interleaved (re, im) float pairs, row-major
  *     [batch][m][n]; m = rows (the paper's index j), n = columns (index k).
  *   - Pointers are DEVICE pointers unless the name ends in _host.
- *   - The caller owns every buffer. Only *_plan_create allocates device memory
- *     (and frees it in *_plan_destroy); no other call allocates, so execute
- *     calls can be captured into a HIP graph.
+ *   - The caller owns every buffer. Only *_plan_create (and the batched
+ *     autotuner, per candidate plan) allocates device memory (freed in
+ *     *_plan_destroy); no other call allocates. ctv_denoise (every schedule),
+ *     ctv_denoise_backward, pr_prox_grad with a fixed step and the stage entry
+ *     points enqueue kernels only, so they can be captured into a HIP graph;
+ *     ctv_denoise_batched is itself one graph launch, and the autotuners and
+ *     pr_prox_grad's line search synchronise the host.
  *   - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL = the
  *     default stream). They return after enqueueing work.
  *   - Arguments are validated before any device work; on error nothing is

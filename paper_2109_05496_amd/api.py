@@ -25,6 +25,16 @@ def _require_cuda(t, name, dtype=None):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _out_like(out, b):
+    """The output tensor: ``out`` (complex64, contiguous, b's shape) or a new one."""
+    if out is None:
+        return torch.empty_like(b)
+    _require_cuda(out, "out", torch.complex64)
+    if tuple(out.shape) != tuple(b.shape):
+        raise ValueError(f"out must have shape {tuple(b.shape)}, got {tuple(out.shape)}")
+    return out
+
+
 def _lams(lam, batch):
     if isinstance(lam, torch.Tensor):
         lam = lam.detach().cpu().reshape(-1).tolist()
@@ -80,8 +90,7 @@ def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, it
         _require_cuda(support, "support", torch.uint8)
         if tuple(support.shape) != (m, n):
             raise ValueError("support must be [m, n]")
-    x = out if out is not None else torch.empty_like(bb)
-    _require_cuda(x, "out", torch.complex64)
+    x = _out_like(out, b)
     ws_bytes, sv_bytes = workspace_size(m, n, B, kind, alpha, constraint, iters, fuse, ckpt_every, method)
     ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     g = torch.empty(B, dtype=torch.float64, device=dev) if gap else None
@@ -93,7 +102,6 @@ def denoise(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, it
     call("ctv_denoise", ctypes.byref(p), B, m, n, _ptr(bb), _lams(lam, B), _ptr(support), _ptr(x),
          _ptr(g), _ptr(state), int(k0), _ptr(st_out), int(ckpt_every), _ptr(saved), _ptr(ws),
          ws.numel(), _stream(dev))
-    x = x[0] if squeeze else x
     res = [x]
     if gap:
         res.append(g)
@@ -211,8 +219,7 @@ def autotune(b, lam, kind="1i", alpha=0.5, constraint="modulus", support=None, i
     p = make_params(kind, alpha, constraint, iters, 0, method=method)
     if support is not None:
         _require_cuda(support, "support", torch.uint8)
-    x = out if out is not None else torch.empty_like(bb)
-    _require_cuda(x, "out", torch.complex64)
+    x = _out_like(out, b)
     ws_bytes, _ = workspace_size(m, n, B, kind, alpha, constraint, iters, 0, 0, method)
     ws = workspace if workspace is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     res = (_lib.Tuning * _MAX_CANDIDATES)()
