@@ -202,7 +202,7 @@ ctv_status ctv_batched_plan_tiling(const ctv_batched_plan* plan, int32_t* fuse_o
  * plain call without gap, state or checkpoints) once per candidate (tile
  * shape, fuse) pair, times `reps` further calls of each on `stream` with HIP
  * events (median), and records the fastest in a process-wide table keyed by
- * the device's architecture and CU count and by (tv_kind, constraint, method,
+ * the device's architecture, its CU count and the HIP runtime version, and by (tv_kind, constraint, method,
  * batch, m, n, iters); the support mask is not part of the key. ctv_denoise,
  * ctv_tiling and pr_prox_grad (its inner prox) use a recorded entry whenever
  * params.fuse, tile_waves and tile_rows are all 0 (and schedule is not

@@ -49,7 +49,8 @@ struct Fnv {
   }
 };
 
-// Architecture name and CU count of the current device ("" when there is none).
+// Architecture name and CU count of the current device and the HIP runtime
+// version ("" when there is no device).
 // Caller holds g_mu.
 std::string device_identity_locked() {
   int dev = 0;
@@ -64,7 +65,13 @@ std::string device_identity_locked() {
     (void)hipGetLastError();
     return std::string();
   }
-  std::string id = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+  int rt = 0;
+  if (hipRuntimeGetVersion(&rt) != hipSuccess) {
+    (void)hipGetLastError();
+    rt = 0;
+  }
+  std::string id = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu/hip" +
+                   std::to_string(rt);
   g_dev_ident[dev] = id;
   return id;
 }
