@@ -116,3 +116,37 @@ def test_batched_autotune_plan_uses_choice():
     other = ctv().BatchedPlan(imgs[:3])
     assert other.tiling == (8, 8, 8)
     other.close()
+
+
+def saved_table_entries():
+    """(kind, fuse, tile) of the saved MI355X table's entries for the masked
+    2048^2, K = 200 benchmark problem, read from the text of the table."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2109_05496_amd",
+                        "tuning", "mi355x.jsonl")
+    out = []
+    for line in open(path):
+        if not line.strip():
+            continue
+        e = json.loads(line)
+        words = e["what"].split()
+        if words[0] == "plain" and "m=2048" in words and "n=2048" in words and "K=200" in words:
+            out.append((words[1], e["fuse"], (e["tile_waves"], e["tile_rows"])))
+    return out
+
+
+def test_benchmark_configuration_at_full_size_equals_default():
+    """The masked 2048^2 four-kind workload in the launch configuration the
+    benchmark runs (the saved table's entries) gives the same bits as the
+    default configuration, which the corner-crop test pins to the oracle."""
+    entries = saved_table_entries()
+    assert sorted(k for k, _, _ in entries) == ["1a", "1i", "2a", "2i"]
+    c = synth.config2(0)
+    bt, mt = torch.as_tensor(c["b"]).cuda(), torch.as_tensor(c["mask"]).cuda()
+    for kind, fuse, tile in entries:
+        args = dict(kind=kind, alpha=c["alpha"], support=mt, iters=c["iters"])
+        x_default = ctv().denoise(bt, c["lam"], fuse=8, tile=(8, 8), **args)
+        x_bench = ctv().denoise(bt, c["lam"], fuse=fuse, tile=tile, **args)
+        torch.cuda.synchronize()
+        assert torch.equal(f32(x_bench), f32(x_default)), (kind, fuse, tile)
