@@ -223,9 +223,19 @@ def bench_pr(ctv, synth, torch, dev, tuner, reps=2):
 
     ms = timed(run, reps, torch, stream)
     fgp_px_it = m * m * P["outer"] * P["inner"]
+
+    def loss_trace(accelerate):
+        """Data term F after outer iterations 1, 10, 50, 100 (Algorithm 1 vs
+        the plain proximal gradient of Eq. 14, the comparison of Fig. 5)."""
+        _, lt = ctv.phase_retrieval(y, P["distances"], P["wavelength"], P["pixel"], tau=P["tau"], gamma=P["gamma"],
+                                    outer=P["outer"], inner=P["inner"], accelerate=accelerate, loss=True)
+        lt = lt.cpu().numpy()
+        return {f"F_{k}": float(lt[k - 1]) for k in (1, 10, 50, P["outer"]) if k <= len(lt)}
+
     return {"workload": "1024^2, D=4, 100 outer x 20 FGP iterations, type-1i, |x|<=1",
             "prox_tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "ms": round(ms, 3), "ms_per_outer_iteration": round(ms / P["outer"], 4),
-            "fgp_Mpx_it_s_equiv": round(fgp_px_it / ms / 1e3, 1), "fft2_per_outer_iteration": 2 * len(P["distances"]) + 2}
+            "fgp_Mpx_it_s_equiv": round(fgp_px_it / ms / 1e3, 1), "fft2_per_outer_iteration": 2 * len(P["distances"]) + 2,
+            "data_term_fista_vs_ista": {"fista": loss_trace(True), "ista": loss_trace(False)}}
 
 
 def median_ms(fn, reps, torch, stream, before=None):
