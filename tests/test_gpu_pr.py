@@ -193,3 +193,32 @@ def test_line_search_and_warm_start_config5():
     assert np.all(np.diff(s) <= 0) and s[0] <= 1.0
     assert lo[-1] < lo[0]
     assert float(x.abs().max()) <= 1 + 1e-6
+
+
+@pytest.mark.parametrize("m,n", [(64, 128), (128, 32)])
+def test_non_square_problem_matches_oracle(m, n):
+    """m != n exercises the transposed spectrum layout ([n][m]) and the
+    transposed transfer-function tables: propagation, gradient and one FISTA
+    iteration against the oracle."""
+    big = synth.config5_object(seed=9, size=max(m, n), n_shapes=10, sigma_px=2.0)
+    truth = big[:m, :n]
+    dists = P5["distances"][:3]
+    Hs = [opr.transfer(m, n, d, P5["wavelength"], P5["pixel"]) for d in dists]
+    rng = np.random.default_rng(9)
+    y = np.stack([synth.poisson_measure(np.abs(opr.A(truth, H)) ** 2, P5["photons"], rng) for H in Hs])
+    # the same kind of test point as the square case above: away from the
+    # truth's modulus, so the residual |A x| - sqrt(y) does not cancel to the
+    # noise level (which would scale FP32 rounding by the cancellation)
+    x = (truth * np.exp(0.2j) + 0.05).astype(np.complex64)
+    out = ctv().pr_forward(dev(x), dists, P5["wavelength"], P5["pixel"]).cpu().numpy()
+    for d, H in enumerate(Hs):
+        assert rel(out[d], opr.A(x.astype(np.complex128), H)) <= 2e-6, d
+    g, loss = ctv().pr_gradient(dev(x), dev(y), dists, P5["wavelength"], P5["pixel"])
+    sy = [np.sqrt(np.maximum(yy.astype(np.float64), 0)) for yy in y]
+    assert rel(g.cpu().numpy(), opr.grad_F(x.astype(np.complex128), sy, Hs)) <= 1e-5
+    lref = opr.data_term(x.astype(np.complex128), sy, Hs)
+    assert abs(float(loss.cpu()[0]) - lref) <= 1e-5 * lref
+    xg = ctv().phase_retrieval(dev(y), dists, P5["wavelength"], P5["pixel"], tau=0.02, gamma=0.4, outer=1, inner=7,
+                               kind="2i").cpu().numpy()
+    xo, _ = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 1, 7, 0.02, 0.4, "2i")
+    assert rel(xg, xo) <= 1e-5, rel(xg, xo)
