@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -421,9 +422,11 @@ ctv_status ctv_tune_cache_load(const char* path) {
                     field_num(line, "ms", &ms);
     char* end = nullptr;
     const unsigned long long k = ok ? std::strtoull(key.c_str(), &end, 16) : 0;
-    TileShape ts{(int)w, (int)r};
-    if (!ok || key.empty() || (end && *end) || arch.empty() || T < 1 || T > kMaxFuse || T != (int)T ||
-        w != (int)w || r != (int)r || ts.waves <= 0 || !valid_tile_shape(ts))
+    // range and integrality are checked on the doubles, before any conversion
+    auto small_int = [](double v, int lo, int hi) { return v >= lo && v <= hi && v == std::floor(v); };
+    const bool nums = small_int(T, 1, kMaxFuse) && small_int(w, 1, 64) && small_int(r, 1, 64);
+    const TileShape ts{nums ? (int)w : 0, nums ? (int)r : 0};
+    if (!ok || key.empty() || (end && *end) || arch.empty() || !nums || !valid_tile_shape(ts))
       return fail(CTV_ERR_INVALID_ARG, std::string(path) + ":" + std::to_string(lineno) + ": malformed tuning entry");
     (void)field_str(line, "what", &what);
     TuneEntry e;

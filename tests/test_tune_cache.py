@@ -54,7 +54,8 @@ def test_table_round_trip(tmp_path):
 
 @pytest.mark.parametrize("bad", [
     dict(fuse=0), dict(fuse=17), dict(fuse=2.5), dict(tile_waves=8, tile_rows=16), dict(tile_waves=-1),
-    dict(tile_waves=4, tile_rows=4), dict(key="xyz"), dict(arch=""),
+    dict(tile_waves=4, tile_rows=4), dict(key="xyz"), dict(arch=""), dict(tile_waves=99999999999),
+    dict(fuse=1e300), dict(tile_rows=-1e12),
 ])
 def test_malformed_table_rejected_whole(tmp_path, bad):
     path = tmp_path / "bad.jsonl"
