@@ -122,6 +122,23 @@ __device__ __forceinline__ float4 dual_step(float4 r, float2 y, float2 down, flo
   return g;
 }
 
+// Streaming (non-temporal) stores, used for the forward tile's dual state and
+// x: they leave less dirty data in the L2 caches to be written back at the
+// kernel boundary (measured: +2 % at 2048^2). Loads keep the default policy,
+// since a tile's halo is re-read by its neighbours through L2; the r history
+// and the adjoint state, re-read soon by the same XCD, measured slower when
+// streamed and keep plain stores.
+__device__ __forceinline__ void store_nt(float4* p, float4 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+  __builtin_nontemporal_store(v.z, &p->z);
+  __builtin_nontemporal_store(v.w, &p->w);
+}
+__device__ __forceinline__ void store_nt(float2* p, float2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // Consecutive workgroup ids are spread round-robin over the 8 XCDs of an
 // MI355X; give each XCD one contiguous range of tiles so neighbouring tiles
 // (which re-read each other's halos) share an L2.

@@ -178,7 +178,7 @@ __device__ __forceinline__ float4 ld_state(const float4* p) {
 template <bool COH>
 __device__ __forceinline__ void st_state(float4* p, float4 v) {
   if (!COH) {
-    *p = v;
+    store_nt(p, v);
     return;
   }
   unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
@@ -315,7 +315,7 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
           left = has_left ? left : zero2;
         }
         const float2 xv = proj_c<CONSTR>(dual_to_primal(b[i], q[i], up, left, J.lam), inside[i]);
-        if (col_out && (!BORDER || j < J.m)) J.x[(long long)j * J.n + k] = xv;
+        if (col_out && (!BORDER || j < J.m)) store_nt(J.x + (long long)j * J.n + k, xv);
       }
     }
   }
