@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=12)
+    ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (batched ragged workload, ...)")
     ap.add_argument("--copy-probe", action="store_true",
