@@ -303,3 +303,24 @@ def test_empty_support_and_large_lambda():
         x = gpu_denoise(b, 50.0, kind=kind, iters=60)
         xo = tv.fgp(b.astype(np.complex128), 50.0, 60, kind)
         assert rel(x, xo) <= TOL, kind
+
+
+def test_8192_full_size_against_oracle_on_crops():
+    """The out-of-cache benchmark size (masked 8192^2, K = 48; 2 GiB of dual
+    state, so every state offset is past 2^31 bytes): two opposite corners and
+    one interior window, each checked exactly as in the 2048^2 crop test."""
+    c = synth.config2(0, size=8192)
+    b, mask, K = c["b"], c["mask"], 48
+    m, n = b.shape
+    S, margin = 200, K + 2
+    bt, mt = dev(b), dev(mask)
+    for kind in ("1i", "2a"):
+        x = ctv().denoise(bt, c["lam"], kind=kind, alpha=c["alpha"], support=mt, iters=K).cpu().numpy()
+        for r0, c0 in ((0, 0), (m - S, n - S), (5003, 3001)):
+            xo = tv.fgp(b[r0:r0 + S, c0:c0 + S].astype(np.complex128), c["lam"], K, kind, c["alpha"], "modulus",
+                        mask[r0:r0 + S, c0:c0 + S])
+            rs = slice(0 if r0 == 0 else margin, S if r0 == m - S else S - margin)
+            cs = slice(0 if c0 == 0 else margin, S if c0 == n - S else S - margin)
+            got = x[r0:r0 + S, c0:c0 + S][rs, cs]
+            assert rel(got, xo[rs, cs]) <= TOL, (kind, r0, rel(got, xo[rs, cs]))
+        del x
