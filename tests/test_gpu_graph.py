@@ -129,3 +129,21 @@ def test_phase_retrieval_fixed_step_graph_replays_match_eager():
         torch.cuda.synchronize()
         assert torch.equal(bits(x_cap), bits(x)), f"replay {rep}"
         assert torch.equal(bits(loss_cap), bits(loss)), f"replay {rep}"
+
+
+def test_autotune_refuses_stream_capture():
+    """The autotuner synchronises the host, so it returns an error (before any
+    device work) when its stream is being captured; the capture itself stays
+    usable."""
+    b = torch.as_tensor(noisy(64, 96, 3)).cuda()
+    counter = torch.zeros(1, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        counter.add_(1.0)
+        with pytest.raises(ctv().CtvError) as err:
+            ctv().autotune(b, 0.1, iters=5, reps=1)
+    assert "capture" in str(err.value)
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    assert float(counter.cpu()) == 3.0
