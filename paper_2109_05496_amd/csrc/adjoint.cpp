@@ -100,10 +100,13 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
   }
 
   // Recomputation runs the fused column-tile kernel (default shape), storing
-  // r after every iteration; results do not depend on the tiling.
+  // r after every iteration; results do not depend on the tiling. A segment
+  // of up to 12 iterations is recomputed in one launch (16 x 512^2, c = 10:
+  // one launch of 9-10 iterations per segment instead of two measured 5 %
+  // faster over the whole backward pass).
   Tiling tl;
   ctv_params tp = *p;
-  tp.fuse = 0;
+  tp.fuse = std::min(c, 12);
   tp.tile_waves = 0;
   tp.tile_rows = 0;
   tp.iters = c;
