@@ -8,7 +8,7 @@
 
 namespace ctv {
 
-constexpr int kMaxRev = 4;  // reverse steps fused per launch
+constexpr int kMaxRev = 5;  // reverse steps fused per launch
 
 struct AdjStepArgs {
   const float* b;           // chunk base, complex64

@@ -426,8 +426,10 @@ __device__ __forceinline__ void adj_job_common(const AdjStepArgs& A, int& img, A
   J.steps = A.steps;
 }
 
+// Occupancy pinned at 4 waves per SIMD: left free, the type-1a and type-2i
+// variants with the modulus bound take a few registers more and drop to 3.
 template <int KIND, int CONSTR, bool MASK>
-__global__ __launch_bounds__(kNW * 64) void adj_step_kernel(AdjStepArgs A) {
+__global__ __launch_bounds__(kNW * 64) __attribute__((amdgpu_waves_per_eu(4))) void adj_step_kernel(AdjStepArgs A) {
   __shared__ float2 sX1[kNW * kRW], sX2[kNW * kRW], sX3[kNW * kRW], sX4[kNW * kRW];
   __shared__ double red[kNW];
   int img;
