@@ -486,13 +486,18 @@ __global__ __launch_bounds__(256) void pc_vjp_kernel(const float2* __restrict__ 
   gb[i] = proj_c_vjp<CONSTR>(b[i], s, in, xbar[i]);
 }
 
-__global__ void lam_final_kernel(const double* __restrict__ acc, int tiles_per_img, int batch,
-                                 float* __restrict__ out) {
-  const int img = blockIdx.x * blockDim.x + threadIdx.x;
-  if (img >= batch) return;
+// One wave per image: lane l sums the tiles l, l + 64, ... in order, then the
+// lanes are combined by a fixed butterfly, so the summation order (and the
+// result) is the same on every run.
+__global__ __launch_bounds__(64) void lam_final_kernel(const double* __restrict__ acc, int tiles_per_img,
+                                                       int batch, float* __restrict__ out) {
+  const int img = blockIdx.x;
+  const int lane = threadIdx.x;
   double s = 0.0;
-  for (int t = 0; t < tiles_per_img; ++t) s += acc[(long long)img * tiles_per_img + t];
-  out[img] = (float)s;
+  for (int t = lane; t < tiles_per_img; t += 64) s += acc[(long long)img * tiles_per_img + t];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0 && img < batch) out[img] = (float)s;
 }
 
 }  // namespace
@@ -548,7 +553,7 @@ hipError_t launch_pc_vjp(const float* b, const uint8_t* mask, const float* xbar,
 }
 
 hipError_t launch_lam_final(const double* acc, int tiles_per_img, int batch, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(lam_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, acc, tiles_per_img, batch, out);
+  hipLaunchKernelGGL(lam_final_kernel, dim3((unsigned)batch), dim3(64), 0, s, acc, tiles_per_img, batch, out);
   return hipGetLastError();
 }
 
