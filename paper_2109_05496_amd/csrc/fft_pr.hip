@@ -482,21 +482,30 @@ __global__ __launch_bounds__(256) void fista_kernel(const float2* __restrict__ x
   xprev[p] = xv;
 }
 
-__global__ void loss_final_kernel(const double* __restrict__ partial, int count, float* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Sum of partial[i * stride + j] over i < count by one wave: lane l adds the
+// terms l, l + 64, ... in order, then a fixed butterfly combines the lanes,
+// so the summation order (and the result) is the same on every run.
+__device__ __forceinline__ double wave_sum_strided(const double* __restrict__ partial, int count,
+                                                   long long stride, int j) {
   double s = 0.0;
-  for (int i = 0; i < count; ++i) s += partial[i];
-  *out = (float)s;
+  for (int i = (int)threadIdx.x; i < count; i += 64) s += partial[(long long)i * stride + j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
 }
 
-// out[j] = sum_i partial[i * stride + j] for j < width, in index order (deterministic).
-__global__ void sum_d_kernel(const double* __restrict__ partial, int count, int stride, int width,
-                             double* __restrict__ out) {
-  const int j = threadIdx.x;
-  if (blockIdx.x != 0 || j >= width) return;
-  double s = 0.0;
-  for (int i = 0; i < count; ++i) s += partial[(long long)i * stride + j];
-  out[j] = s;
+__global__ __launch_bounds__(64) void loss_final_kernel(const double* __restrict__ partial, int count,
+                                                        float* __restrict__ out) {
+  const double s = wave_sum_strided(partial, count, 1, 0);
+  if (threadIdx.x == 0) *out = (float)s;
+}
+
+// out[j] = sum_i partial[i * stride + j] for j < width (one wave per j; deterministic).
+__global__ __launch_bounds__(64) void sum_d_kernel(const double* __restrict__ partial, int count, int stride,
+                                                   int width, double* __restrict__ out) {
+  const int j = blockIdx.x;
+  const double s = wave_sum_strided(partial, count, stride, j);
+  if (threadIdx.x == 0 && j < width) out[j] = s;
 }
 
 __global__ __launch_bounds__(256) void fill_f32_kernel(float* __restrict__ p, float v, long long count) {
@@ -672,7 +681,8 @@ hipError_t launch_fill_f32(float* p, float v, long long count, hipStream_t s) {
 }
 
 hipError_t launch_sum_d(const double* partial, int count, int stride, int width, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_d_kernel, dim3(1), dim3(64), 0, s, partial, count, stride, width, out);
+  if (width < 1) return hipSuccess;
+  hipLaunchKernelGGL(sum_d_kernel, dim3((unsigned)width), dim3(64), 0, s, partial, count, stride, width, out);
   return hipGetLastError();
 }
 

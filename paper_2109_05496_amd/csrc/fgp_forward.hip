@@ -688,13 +688,16 @@ __global__ __launch_bounds__(256) void gap_partial_kernel(const float2* __restri
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void gap_final_kernel(const double* __restrict__ partial, int blocks_per_img,
-                                 GapArgs L, double* __restrict__ gap, int batch) {
-  const int img = threadIdx.x;
-  if (img >= batch) return;
+// One wave per image: lane l adds the blocks l, l + 64, ... in order, then a
+// fixed butterfly combines the lanes (the same summation order on every run).
+__global__ __launch_bounds__(64) void gap_final_kernel(const double* __restrict__ partial, int blocks_per_img,
+                                                       GapArgs L, double* __restrict__ gap, int batch) {
+  const int img = blockIdx.x;
   double s = 0.0;
-  for (int i = 0; i < blocks_per_img; ++i) s += partial[img * blocks_per_img + i];
-  gap[img] = (double)L.lam[img] * s;
+  for (int i = (int)threadIdx.x; i < blocks_per_img; i += 64) s += partial[img * blocks_per_img + i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0 && img < batch) gap[img] = (double)L.lam[img] * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -872,7 +875,7 @@ hipError_t launch_gap(const float* x, const float* state, int m, int n, int batc
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gap_final_kernel, dim3(1), dim3(64), 0, s, partial, blocks_per_img, lam,
+  hipLaunchKernelGGL(gap_final_kernel, dim3((unsigned)batch), dim3(64), 0, s, partial, blocks_per_img, lam,
                      gap, batch);
   return hipGetLastError();
 }
