@@ -295,6 +295,57 @@ def median_ms(fn, reps, torch, stream, before=None):
     return times[len(times) // 2]
 
 
+def live_tile_px(mask, halo, rows):
+    """Output pixels of the tiles that ctv_denoise runs for a support (cold
+    start, column tiles of rows x 64 with this halo): a tile runs if its output
+    holds a pixel that is in the support or has a support pixel below or to the
+    right. Returns (live tiles, tiles, live output pixels)."""
+    import numpy as np
+    mk = np.asarray(mask).astype(bool)
+    m, n = mk.shape
+    live = mk.copy()
+    live[:-1, :] |= mk[1:, :]
+    live[:, :-1] |= mk[:, 1:]
+    OW, OH = 64 - 2 * halo, rows - 2 * halo
+    ty, tx = -(-m // OH), -(-n // OW)
+    pad = np.zeros((ty * OH, tx * OW), bool)
+    pad[:m, :n] = live
+    tl = pad.reshape(ty, OH, tx, OW).any(axis=(1, 3))
+    hr = np.minimum(OH, m - OH * np.arange(ty))
+    wc = np.minimum(OW, n - OW * np.arange(tx))
+    return int(tl.sum()), int(tl.size), int((np.outer(hr, wc) * tl).sum())
+
+
+def bench_without_skip(ctv, c, torch, dev, b, mask, x, ws, run_kind, args, per_kind_ms, by_kind):
+    """The same four solves with every tile run: a warm start from an all-zero
+    dual state is the cold start's iteration, but ctv_denoise builds live-tile
+    lists only for cold starts. Results must be bitwise those of the timed run."""
+    m, n = c["b"].shape
+    K = args.iters
+    zero = torch.zeros((1, 2, m, n, 4), dtype=torch.float32, device=dev)
+    xd = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+    same, dense = True, {}
+    for kind in c["kinds"]:
+        def dense_run():
+            ctv.denoise(b, c["lam"], kind=kind, alpha=c["alpha"], constraint=c["constraint"], support=mask,
+                        iters=K, fuse=args.fuse, out=xd, workspace=ws, state=zero, k0=0)
+        dense[kind] = timed(dense_run, max(1, args.steps), torch, stream)
+        run_kind(kind)
+        torch.cuda.synchronize()
+        same = same and torch.equal(xd.view(torch.float32), x.view(torch.float32))
+    T, (tw, tr) = by_kind["1i"]["fuse"], by_kind["1i"]["tile"]
+    live_tiles, all_tiles, live_px = live_tile_px(c["mask"], T, tw * tr)
+    dense_ms = sum(dense.values())
+    skip_ms = sum(per_kind_ms.values()) / args.steps
+    return {"what": "tiles whose outputs lie where the dual stays zero (outside the support, no support pixel "
+                    "below or right) are not run; every tile run instead:",
+            "live_tiles": [live_tiles, all_tiles], "computed_px_frac": round(live_px / (m * n), 4),
+            "every_tile_ms_per_step": round(dense_ms, 3),
+            "every_tile_Mpx_it_s": round(len(c["kinds"]) * m * n * K / dense_ms / 1e3, 1),
+            "speedup": round(dense_ms / skip_ms, 3), "bitwise_equal": bool(same)}
+
+
 def bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, tuner, reps=5):
     """The same masked 2048^2 workload (four kinds x 200 iterations) submitted
     as one ragged batched plan (one HIP graph) instead of four plain calls:
@@ -361,11 +412,14 @@ def bench_out_of_cache(ctv, synth, torch, dev, tuner, size=8192, iters=48, reps=
     warm = median_ms(run, reps, torch, stream)
     cold = median_ms(run, reps, torch, stream, before=lambda: flush.fill_(1.0))
     px_it = size * size * iters
+    _, _, live_px = live_tile_px(c["mask"], T, tw * tr)
+    run_px_it = live_px * iters       # pixel-iterations actually computed (tiles outside the support skipped)
     return {"workload": f"masked {size}x{size} complex64, type-1i, K={iters}",
             "tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "warm_ms": round(warm, 3),
             "cold_ms": round(cold, 3), "warm_Mpx_it_s": round(px_it / warm / 1e3, 1),
-            "cold_Mpx_it_s": round(px_it / cold / 1e3, 1),
-            "cold_hbm_effective_frac": round(px_it * BYTES_PER_PX_IT_MASKED / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+            "cold_Mpx_it_s": round(px_it / cold / 1e3, 1), "computed_px_frac": round(live_px / (size * size), 4),
+            "cold_hbm_effective_frac": round(run_px_it * BYTES_PER_PX_IT_MASKED / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                             3)}
 
 
 def main():
@@ -430,15 +484,20 @@ def main():
 
     # Roofline of the dominant kernel: the fused tile kernel (one instantiation
     # per TV kind; every launch in the timed region is one of them, so the
-    # average launch duration is the kind's event time over its launch count).
+    # average launch duration is the kind's event time over its launch count,
+    # which also holds the two small live-tile scans of the call). The work of
+    # a launch is what it computes: the output pixels of the live tiles (tiles
+    # outside the support are not run) times its fused iterations.
     dom = max(kinds, key=lambda k: per_kind_ms[k])
     T, (tw, tr) = by_kind[dom]["fuse"], by_kind[dom]["tile"]
     launches = math.ceil(K / T)
     kname = f"void ctv::fgp_col_kernel<{KIND_INDEX[dom]}, 1, true, {tw}, {tr}, false>(ctv::FgpPlainArgs)"
     avg_launch_s = per_kind_ms[dom] / args.steps / launches * 1e-3
-    alg_bytes_launch = BYTES_PER_PX_IT_MASKED * m * n * K / launches
-    alg_flops_launch = FLOPS_PER_PX_IT[dom] * m * n * K / launches
-    alg_ops_launch = OPS_PER_PX_IT[dom] * m * n * K / launches
+    live_tiles, all_tiles, live_px = live_tile_px(c["mask"], T, tw * tr)
+    run_px_it = live_px * K               # computed pixel-iterations of one kind
+    alg_bytes_launch = BYTES_PER_PX_IT_MASKED * run_px_it / launches
+    alg_flops_launch = FLOPS_PER_PX_IT[dom] * run_px_it / launches
+    alg_ops_launch = OPS_PER_PX_IT[dom] * run_px_it / launches
     achieved_gbs = alg_bytes_launch / avg_launch_s / 1e9
     achieved_tflops = alg_flops_launch / avg_launch_s / 1e12
     achieved_gops = alg_ops_launch / avg_launch_s / 1e9
@@ -451,6 +510,7 @@ def main():
             "traffic": kp["traffic_bytes"] if kp else None,
             "kernel": kname, "fused_iters": T, "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "alg_ops_per_launch": int(alg_ops_launch),
+            "live_tiles": [live_tiles, all_tiles], "computed_px_frac": round(live_px / (m * n), 4),
             "fp32_flops": {"achieved": round(achieved_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
                            "alg_flops_per_launch": int(alg_flops_launch)},
@@ -471,6 +531,8 @@ def main():
            "per_kind_ms": {k: round(v / args.steps, 3) for k, v in per_kind_ms.items()},
            "wall_s": round(wall, 3),
            "roofline": roof}
+    out["dead_tile_skip"] = bench_without_skip(ctv, c, torch, dev, b, mask, x, ws, run_kind, args, per_kind_ms,
+                                               by_kind)
     if not args.no_extras:
         if args.size == 2048 and K == 200:
             x_plain = {}

@@ -130,17 +130,24 @@ int gap_blocks_per_image(long long px) {
 // Largest halo of the 8 x 8 tile (fuse <= 16): bounds the flow bookkeeping.
 static int flow_max_halo() { return kMaxFuse; }
 
+// Live-tile lists: tilings whose output tiles are at least 16 x 16 pixels have
+// at most live_cap tiles; each of kLiveSlots tilings keeps flags[cap] and
+// live[1 + cap].
+constexpr int kLiveSlots = 3;
+static long long live_cap(int m, int n) { return (long long)((m + 15) / 16) * ((n + 15) / 16); }
+static size_t live_ints(int m, int n) { return (size_t)kLiveSlots * (2 * live_cap(m, n) + 1); }
+
 size_t denoise_ws_bytes(int batch, int m, int n) {
   const size_t st = align_up(state_bytes(batch, m, n));
   const size_t gap = align_up((size_t)batch * gap_blocks_per_image((long long)m * n) * sizeof(double));
   const size_t flow = align_up((size_t)flow_ints(std::min(batch, kPlainChunk), m, n, flow_max_halo()) * 4);
-  return 2 * st + gap + flow;
+  return 2 * st + gap + flow + align_up(live_ints(m, n) * 4);
 }
 
 ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int n, const float* b,
                       const uint8_t* support, const float* lam, const std::vector<float>& beta, int k, int Tl,
                       const float* src, float* dst, float* x, hipStream_t s, float* r_hist,
-                      long long r_hist_stride) {
+                      long long r_hist_stride, const int* live) {
   if (r_hist && (tl.shape.waves != 8 || tl.shape.rows_per_thread != 8))
     return fail(CTV_ERR_INVALID_ARG, "r history needs the 8 x 8 column tile");
   FgpPlainArgs a;
@@ -159,6 +166,9 @@ ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int 
   a.x = x;
   a.r_hist = r_hist;
   a.r_hist_stride = r_hist_stride;
+  if (live && (tl.shape.waves <= 0 || r_hist))
+    return fail(CTV_ERR_INVALID_ARG, "internal: live-tile lists need the column tiles");
+  a.live = live;
   a.T = Tl;
   a.halo = std::max(1, Tl + (x ? 1 : 0));
   for (int i = 0; i < kMaxFuse; ++i) a.beta[i] = (i < Tl) ? beta[(size_t)(k + 1 + i)] : 0.0f;
@@ -244,6 +254,9 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
   double* partial = reinterpret_cast<double*>(wsb + 2 * align_up(st_full));
   int* flow_mem = reinterpret_cast<int*>(
       wsb + 2 * align_up(st_full) + align_up((size_t)batch * gap_blocks_per_image(px) * sizeof(double)));
+  int* live_mem = reinterpret_cast<int*>(
+      reinterpret_cast<char*>(flow_mem) +
+      align_up((size_t)flow_ints(std::min(batch, kPlainChunk), m, n, flow_max_halo()) * 4));
   Tiling tl;
   st = choose_tiling(p, m, n, batch, &tl, p->schedule != CTV_S_FLOW);
   if (st) return st;
@@ -338,24 +351,73 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
         src = fa.st_out ? fa.st_out : last_state;
         k += Kc;
       }
-    } else do {
-      const int seg_end = ckpt_every > 0 ? std::min(kend, (k / ckpt_every + 1) * ckpt_every) : kend;
-      const int Tl = even_split(tl.T, seg_end - k);
-      const bool last = (k + Tl == kend);
-      float* dst;
-      float* other = (src == bufA + st_off) ? bufB + st_off : bufA + st_off;
-      if (last)
-        dst = state_out ? state_out + st_off : (gap ? other : nullptr);
-      else if (ckpt_every > 0 && (k + Tl) % ckpt_every == 0)
-        dst = saved + (size_t)((k + Tl) / ckpt_every - 1) * (st_full / 4) + st_off;
-      else
-        dst = other;
-      st = fgp_launch(p, tl, cb, m, n, b + 2 * img_px, support, lambda_host + c0, beta, k, Tl, src, dst,
-                      last ? x + 2 * img_px : nullptr, s);
-      if (st) return st;
-      src = dst;
-      k += Tl;
-    } while (k < kend);
+    } else {
+      // With a support and a cold start, the dual stays zero at pixels that
+      // neither lie in the support nor have a support pixel below or to the
+      // right of them (x = 0 there too). Launches that read and write only the
+      // workspace buffers run just the tiles holding other pixels, from a
+      // live-tile list built once per tiling: the first list also stores the
+      // zeros at those pixels of both buffers, the one of the launch that
+      // writes x stores x = 0 in its skipped tiles. Launches into checkpoint
+      // slots or a caller's state buffer run every tile. Results are bitwise
+      // those of running every tile.
+      const bool may_skip = support && !state_in && tl.shape.waves > 0;
+      int slot_h[kLiveSlots], slot_x[kLiveSlots], used = 0;
+      bool zeroed = false;
+      const size_t slot_ints = 2 * live_cap(m, n) + 1;
+      do {
+        const int seg_end = ckpt_every > 0 ? std::min(kend, (k / ckpt_every + 1) * ckpt_every) : kend;
+        const int Tl = even_split(tl.T, seg_end - k);
+        const bool last = (k + Tl == kend);
+        float* dst;
+        float* other = (src == bufA + st_off) ? bufB + st_off : bufA + st_off;
+        if (last)
+          dst = state_out ? state_out + st_off : (gap ? other : nullptr);
+        else if (ckpt_every > 0 && (k + Tl) % ckpt_every == 0)
+          dst = saved + (size_t)((k + Tl) / ckpt_every - 1) * (st_full / 4) + st_off;
+        else
+          dst = other;
+        const int* live = nullptr;
+        const bool dst_ws = !dst || dst == bufA + st_off || dst == bufB + st_off;
+        if (may_skip && dst_ws) {
+          const int H = std::max(1, Tl + (last ? 1 : 0));
+          const int rows = tl.shape.rows();
+          const int OW = 64 - 2 * H, OH = rows - 2 * H;
+          const long long tiles = (long long)((n + OW - 1) / OW) * ((m + OH - 1) / OH);
+          int slot = -1;
+          for (int i = 0; i < used; ++i)
+            if (slot_h[i] == H && slot_x[i] == (last ? 1 : 0)) slot = i;
+          if (slot < 0 && used < kLiveSlots && OW >= 16 && OH >= 16 && tiles <= live_cap(m, n)) {
+            slot = used++;
+            slot_h[slot] = H;
+            slot_x[slot] = last ? 1 : 0;
+            LiveScanArgs la;
+            la.mask = support;
+            la.m = m;
+            la.n = n;
+            la.halo = H;
+            la.rows = rows;
+            la.tiles_x = (n + OW - 1) / OW;
+            la.tiles_y = (m + OH - 1) / OH;
+            la.flags = live_mem + slot * slot_ints;
+            la.zero_st = zeroed ? 0 : 1;
+            la.st0 = bufA + st_off;
+            la.st1 = bufB + st_off;
+            la.x = last ? x + 2 * img_px : nullptr;
+            la.batch = cb;
+            hipError_t e = launch_live_tiles(la, live_mem + slot * slot_ints + live_cap(m, n), s);
+            if (e != hipSuccess) return hip_fail(e, "live-tile scan");
+            zeroed = true;
+          }
+          if (slot >= 0) live = live_mem + slot * slot_ints + live_cap(m, n);
+        }
+        st = fgp_launch(p, tl, cb, m, n, b + 2 * img_px, support, lambda_host + c0, beta, k, Tl, src, dst,
+                        last ? x + 2 * img_px : nullptr, s, nullptr, 0, live);
+        if (st) return st;
+        src = dst;
+        k += Tl;
+      } while (k < kend);
+    }
     if (gap) {
       GapArgs ga;
       for (int i = 0; i < cb; ++i) ga.lam[i] = lambda_host[c0 + i];

@@ -23,8 +23,9 @@ namespace ctv {
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // P_C of one pixel: x / max{1, |x|} (Eq. 26) when the modulus constraint is
-// on, then forced to 0 outside the support (a zero scale, so masked pixels hold
-// exactly +-0).
+// on, then forced to 0 outside the support (a zero scale; adding +0 to the
+// product turns -0 into +0, so masked pixels hold exactly +0 whatever the sign
+// of w, and a tile that is never computed matches one that is).
 template <int CONSTR>
 __device__ __forceinline__ float2 proj_c(float2 w, bool inside) {
   float2 y = w;
@@ -32,8 +33,8 @@ __device__ __forceinline__ float2 proj_c(float2 w, bool inside) {
     const float n2 = fmaf(w.x, w.x, w.y * w.y);
     float s = fminf(1.0f, rsq(n2));  // 1/max{1,|w|}; rsqrt(0) = inf gives 1
     s = inside ? s : 0.0f;
-    y.x = w.x * s;
-    y.y = w.y * s;
+    y.x = fmaf(w.x, s, 0.0f);  // the product, with +0 in place of -0
+    y.y = fmaf(w.y, s, 0.0f);
   } else {
     y.x = inside ? w.x : 0.0f;
     y.y = inside ? w.y : 0.0f;

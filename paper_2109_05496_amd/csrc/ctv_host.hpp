@@ -48,9 +48,11 @@ size_t denoise_ws_bytes(int batch, int m, int n);
 // cold start) into dst (nullptr = not stored); x != nullptr adds Eq. (18).
 // r_hist != nullptr (8 x 8 column tile only) also stores r after each fused
 // iteration i into plane 1 of the state at r_hist + i * r_hist_stride floats.
+// live (column tiles only): the live-tile list of this tiling; the other tiles
+// are not run, so src and dst must already hold their (zero) values.
 ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int n, const float* b,
                       const uint8_t* support, const float* lam, const std::vector<float>& beta, int k, int Tl,
                       const float* src, float* dst, float* x, hipStream_t s, float* r_hist = nullptr,
-                      long long r_hist_stride = 0);
+                      long long r_hist_stride = 0, const int* live = nullptr);
 
 }  // namespace ctv

@@ -26,6 +26,8 @@ struct FgpPlainArgs {
   float* r_hist;         // 8 x 8 column tile only: states [T][chunk][2][m][n][4] whose plane 1
                          // receives r after each fused iteration (output pixels), or nullptr
   long long r_hist_stride;  // floats from one iteration's state to the next
+  const int* live;       // column tiles only: [0] = L, [1 .. L] = the tiles (of one image) to run, or
+                         // nullptr for all; the grid stays one workgroup per tile of the chunk
 };
 
 // Persistent dataflow form of the plain path (8 x 8 column tile): one launch
@@ -121,6 +123,22 @@ hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const T
                             hipStream_t s);
 
 hipError_t launch_zero_f4(float* p, long long count_f4, hipStream_t s);
+
+// Live tiles of a support for one tiling (see live_scan_kernel): flags[tiles]
+// scratch, then live[0] = L and live[1 .. L] the live tiles in increasing order.
+struct LiveScanArgs {
+  const uint8_t* mask;   // [m][n]
+  int m, n;
+  int halo, rows;        // the tiling: regions of rows x 64 with this halo
+  int tiles_x, tiles_y;
+  int* flags;
+  int zero_st;           // store zeros at dead output pixels of st0 and st1
+  float* st0;            // chunk bases of the two state buffers [batch][2][m][n][4]
+  float* st1;
+  float* x;              // chunk base of x [batch][m][n] complex64 (zeroed in dead tiles) or nullptr
+  int batch;
+};
+hipError_t launch_live_tiles(const LiveScanArgs& a, int* live, hipStream_t s);
 hipError_t launch_project_c(const float* b, const uint8_t* mask, float* x, long long px, int batch,
                             int constr, hipStream_t s);
 struct GapArgs {

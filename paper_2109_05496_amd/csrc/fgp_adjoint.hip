@@ -48,7 +48,7 @@ __device__ __forceinline__ float2 proj_c_s(float2 w, bool inside, float& s) {
     const float n2 = fmaf(w.x, w.x, w.y * w.y);
     s = fminf(1.0f, rsq(n2));
     const float sm = inside ? s : 0.0f;
-    return make_float2(w.x * sm, w.y * sm);
+    return make_float2(fmaf(w.x, sm, 0.0f), fmaf(w.y, sm, 0.0f));
   }
   s = 1.0f;
   return make_float2(inside ? w.x : 0.0f, inside ? w.y : 0.0f);

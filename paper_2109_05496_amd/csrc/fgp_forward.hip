@@ -238,12 +238,13 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
     }
   }
 
+  const bool col_out = lane >= H && lane < kRW - H && kin;
+
   // Rows whose q can still reach the output: after the last iteration the
   // stored state needs rows [H, RH-H) and Eq. (18) additionally reads q one row
   // up, so at iteration t the needed rows are [t + eu, RH - t - ed).
   const int ed = H - J.T;
   const int eu = ed - (J.x ? 1 : 0);
-  const bool col_out = lane >= H && lane < kRW - H && kin;
   float2 y[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) y[i] = zero2;
@@ -341,10 +342,27 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ float sBeta[kMaxFuse];
   if (threadIdx.x < kMaxFuse) sBeta[threadIdx.x] = P_.beta[threadIdx.x];
   __syncthreads();
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const int per_img = P_.tiles_x * P_.tiles_y;
-  const int img = tile / per_img;
-  const int t = tile - img * per_img;
+  int img, t;
+  if (P_.live) {
+    // Only the live tiles: entry e of the chunk's images x live tiles is tile
+    // live[1 + e % L] of image e / L, and each XCD takes one contiguous slice of
+    // the entries (equal counts, neighbouring tiles in one L2). Workgroups past
+    // their XCD's slice have nothing to do.
+    const int L = P_.live[0];
+    const int total = (gridDim.x / per_img) * L;
+    constexpr int kXcd = 8;
+    const int x = blockIdx.x % kXcd, i = blockIdx.x / kXcd;
+    const int q = total / kXcd, rem = total % kXcd;
+    if (i >= q + (x < rem ? 1 : 0)) return;
+    const int e = x * q + (x < rem ? x : rem) + i;
+    img = e / L;
+    t = P_.live[1 + (e - img * L)];
+  } else {
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    img = tile / per_img;
+    t = tile - img * per_img;
+  }
   const long long px = (long long)P_.m * P_.n;
   TileJob J;
   J.b = reinterpret_cast<const float2*>(P_.b) + img * px;
@@ -594,6 +612,98 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
     }
     __syncthreads();  // the next tile reuses the LDS rows
   }
+}
+
+// ---------------------------------------------------------------------------
+// Live tiles of a support (cold starts only). From q = 0 the dual stays exactly
+// zero at a pixel outside the support whose lower and right neighbours are
+// outside it too: y vanishes at all three pixels its differences read, so the
+// gradient step adds nothing and P_S(0) = 0; x = 0 there as well. Such pixels
+// are dead. A tile is live if its output holds a pixel that is not dead.
+//
+// live_scan_kernel: one wave per tile of one image (lane = column of the
+// output, plus one column to its right). It writes flags[tile]; with zero_st it
+// also stores zeros at the dead output pixels of both state buffers, for every
+// image of the chunk (so tiles that later launches skip read and keep zeros);
+// with x, a dead tile stores x = 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void live_scan_kernel(LiveScanArgs a) {
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x;
+  const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+  const int OW = kRW - 2 * a.halo, OH = a.rows - 2 * a.halo;
+  const int j0 = ty * OH, k = tx * OW + lane;
+  const bool kin = lane <= OW && k < a.n;
+  const bool kout = lane < OW && k < a.n;
+  const long long px = (long long)a.m * a.n;
+  const int jend = min(j0 + OH, a.m);  // output rows [j0, jend)
+  bool below = (kin && jend < a.m) ? (a.mask[(long long)jend * a.n + k] != 0) : false;
+  bool live = false;
+  for (int j = jend - 1; j >= j0; --j) {
+    const long long p = (long long)j * a.n + k;
+    const bool cur = kin ? (a.mask[p] != 0) : false;
+    const bool right = __shfl_down(cur ? 1 : 0, 1) != 0 && lane < 63;
+    const bool dead = !cur && !below && !right;
+    if (kout) {
+      live = live || !dead;
+      if (a.zero_st && dead) {
+        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int img = 0; img < a.batch; ++img) {
+          const long long base = (long long)img * 2 * px;
+          reinterpret_cast<float4*>(a.st0)[base + p] = z;
+          reinterpret_cast<float4*>(a.st0)[base + px + p] = z;
+          reinterpret_cast<float4*>(a.st1)[base + p] = z;
+          reinterpret_cast<float4*>(a.st1)[base + px + p] = z;
+        }
+      }
+    }
+    below = cur;
+  }
+  const bool tile_live = __builtin_amdgcn_ballot_w64(live) != 0;
+  if (lane == 0) a.flags[t] = tile_live ? 1 : 0;
+  if (!tile_live && a.x && kout) {
+    for (int j = j0; j < jend; ++j)
+      for (int img = 0; img < a.batch; ++img)
+        reinterpret_cast<float2*>(a.x)[(long long)img * px + (long long)j * a.n + k] = make_float2(0.0f, 0.0f);
+  }
+}
+
+// One workgroup: live[0] = number of live tiles, live[1 ..] = their indices in
+// increasing order (each thread takes a contiguous run of flags; a block-wide
+// exclusive scan of the run counts places the runs).
+__global__ __launch_bounds__(1024) void live_list_kernel(const int* __restrict__ flags, int count,
+                                                          int* __restrict__ live) {
+  __shared__ int sWave[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (count + 1023) / 1024;
+  const int lo = min(count, tid * per), hi = min(count, lo + per);
+  int own = 0;
+  for (int i = lo; i < hi; ++i) own += flags[i] != 0;
+  int inc = own;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) sWave[wave] = inc;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int w = 0; w < 16; ++w) {
+    const int v = sWave[w];
+    before += (w < wave) ? v : 0;
+    total += v;
+  }
+  if (tid == 0) live[0] = total;
+  int pos = 1 + before + inc - own;
+  for (int i = lo; i < hi; ++i)
+    if (flags[i] != 0) live[pos++] = i;
+}
+
+hipError_t launch_live_tiles(const LiveScanArgs& a, int* live, hipStream_t s) {
+  const int count = a.tiles_x * a.tiles_y;
+  if (a.halo < 1 || kRW - 2 * a.halo < 1 || a.rows - 2 * a.halo < 1 || count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(live_scan_kernel, dim3(count), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(live_list_kernel, dim3(1), dim3(1024), 0, s, a.flags, count, live);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ import json
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/fgp_forward.hip", "csrc/ctv_device.hpp")
+KERNEL_SOURCES = ("csrc/fgp_forward.hip", "csrc/ctv_device.hpp", "csrc/capi.cpp")
 
 
 def kernel_source_hash():

@@ -1,0 +1,148 @@
+"""Tiles outside the support. With a support mask and a cold start, ctv_denoise
+runs only the tiles whose output holds a pixel where the dual can move (in the
+support, or with a support pixel below or to the right; that the dual stays
+exactly zero everywhere else is pinned on the oracle in test_oracle_fgp.py),
+from a live-tile list built once per tiling. Results must be bitwise those of
+running every tile, which a warm start from an all-zero state does (the lists
+need a cold start). Workspaces are filled with NaN bytes first, so any stale
+state that a skipped tile left behind would show."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import tv
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TOL = 1e-5
+
+
+def ctv():
+    import paper_2109_05496_amd as m
+    return m
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def sparse_mask(m, n):
+    """A block well inside, one pixel in the last row and column, and a strip
+    along the right border: dead tiles in the interior and at every border."""
+    mk = np.zeros((m, n), np.uint8)
+    mk[m // 3:m // 3 + m // 5, n // 4:n // 4 + n // 6] = 1
+    mk[m - 1, n - 1] = 1
+    mk[5:m // 2, n - 3:] = 1
+    return mk
+
+
+def nan_workspace(m, n, B, kind, iters, fuse):
+    ws_bytes, _ = ctv().workspace_size(m, n, B, kind, 0.5, "modulus", iters, fuse, 0, "fgp")
+    return torch.full((ws_bytes,), 0xFF, dtype=torch.uint8, device="cuda")
+
+
+def zero_state(B, m, n):
+    return torch.zeros((B, 2, m, n, 4), dtype=torch.float32, device="cuda")
+
+
+SHAPES = [(8, 8), (8, 4), (4, 8), (16, 4), (16, 8)]
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+def test_skipping_is_bitwise_invisible(kind):
+    m, n = 300, 420
+    rng = np.random.default_rng(41)
+    _, b = synth.denoise_case(m, n, 12, 0.15, rng)
+    mask = dev(sparse_mask(m, n))
+    bt = dev(b)
+    for tile in SHAPES:
+        for fuse, iters in ((3, 20), (8, 37), (9, 30)):
+            kw = dict(kind=kind, support=mask, iters=iters, fuse=fuse, tile=tile)
+            ws = nan_workspace(m, n, 1, kind, iters, fuse)
+            x, g, st = ctv().denoise(bt, 0.07, gap=True, return_state=True, workspace=ws, **kw)
+            xd, gd, std = ctv().denoise(bt, 0.07, gap=True, return_state=True, state=zero_state(1, m, n),
+                                        k0=0, **kw)
+            assert np.array_equal(bits(x), bits(xd)), (tile, fuse)
+            assert np.array_equal(bits(st), bits(std)), (tile, fuse)
+            assert torch.equal(g, gd), (tile, fuse)
+            # the third and later launches reuse both ping-pong buffers; the
+            # gap variant also keeps the final state in one of them
+            xg = ctv().denoise(bt, 0.07, gap=True, workspace=ws, **kw)[0]
+            assert np.array_equal(bits(xg), bits(x)), (tile, fuse)
+
+
+def test_skipping_matches_oracle_and_reused_workspace():
+    """A workspace reused from a call with another support, a batch sharing the
+    support, and the oracle at the stated tolerance."""
+    m, n, K = 200, 260, 30
+    rng = np.random.default_rng(42)
+    bs = np.stack([synth.denoise_case(m, n, 10, 0.15, rng)[1] for _ in range(3)])
+    mk = sparse_mask(m, n)
+    ws = nan_workspace(m, n, 3, "2i", K, 0)
+    full = dev(np.ones((m, n), np.uint8))
+    ctv().denoise(dev(bs), [0.05, 0.08, 0.12], kind="2i", support=full, iters=K, workspace=ws)
+    x = ctv().denoise(dev(bs), [0.05, 0.08, 0.12], kind="2i", support=dev(mk), iters=K, workspace=ws)
+    x = x.cpu().numpy()
+    for i, lam in enumerate((0.05, 0.08, 0.12)):
+        xo = tv.fgp(bs[i].astype(np.complex128), lam, K, "2i", 0.5, "modulus", mk)
+        err = np.linalg.norm(x[i] - xo) / np.linalg.norm(xo)
+        assert err <= TOL, (i, err)
+        assert np.all(x[i][mk == 0] == 0)
+
+
+@pytest.mark.parametrize("kind", ["1i", "2a"])
+def test_checkpoints_with_skipping_equal_resumed_states(kind):
+    """Checkpoint slots are fresh buffers: dead tiles store their zeros there.
+    Slot s holds the state after (s + 1) * c iterations, bitwise as a plain run
+    returns it."""
+    m, n, K, c = 180, 150, 30, 10
+    rng = np.random.default_rng(43)
+    _, b = synth.denoise_case(m, n, 10, 0.15, rng)
+    mk = sparse_mask(m, n)
+    bt, mt = dev(b), dev(mk)
+    x, saved = ctv().denoise(bt, 0.06, kind=kind, support=mt, iters=K, ckpt_every=c)
+    slot = saved.view(-1, 1, 2, m, n, 4)
+    for s in range(slot.shape[0]):
+        _, st = ctv().denoise(bt, 0.06, kind=kind, support=mt, iters=(s + 1) * c, return_state=True)
+        assert np.array_equal(bits(slot[s]), bits(st)), s
+    xn = ctv().denoise(bt, 0.06, kind=kind, support=mt, iters=K)
+    assert np.array_equal(bits(x), bits(xn))
+
+
+def test_tilings_chunks_and_single_launch():
+    """K = 50 with T = 8 runs launches of 8 and 7 iterations and an x launch
+    (three tilings, three lists); K = 5 is one launch that writes x; 33 images
+    are two chunks of the batch, each with its own lists."""
+    m, n = 150, 230
+    rng = np.random.default_rng(44)
+    mk = dev(sparse_mask(m, n))
+    for B, iters in ((1, 50), (1, 5), (33, 12)):
+        bs = np.stack([synth.denoise_case(m, n, 6, 0.15, rng)[1] for _ in range(B)])
+        bt = dev(bs)
+        lams = list(np.linspace(0.04, 0.12, B))
+        ws = nan_workspace(m, n, B, "1a", iters, 8)
+        x = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8, workspace=ws)
+        xd = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8, state=zero_state(B, m, n), k0=0)
+        assert np.array_equal(bits(x), bits(xd)), (B, iters)
+
+
+def test_support_of_one_pixel_and_of_nothing():
+    """All tiles but one (or all) skipped: x is zero outside, the one pixel's
+    neighbourhood matches the oracle."""
+    m, n, K = 130, 190, 25
+    rng = np.random.default_rng(45)
+    _, b = synth.denoise_case(m, n, 6, 0.15, rng)
+    one = np.zeros((m, n), np.uint8)
+    one[77, 101] = 1
+    for mask in (np.zeros((m, n), np.uint8), one):
+        ws = nan_workspace(m, n, 1, "2i", K, 0)
+        x = ctv().denoise(dev(b), 0.1, kind="2i", support=dev(mask), iters=K, workspace=ws).cpu().numpy()
+        xo = tv.fgp(b.astype(np.complex128), 0.1, K, "2i", 0.5, "modulus", mask)
+        assert np.all(x[mask == 0] == 0)
+        assert np.allclose(x, xo, rtol=0, atol=1e-6)

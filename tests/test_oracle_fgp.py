@@ -250,3 +250,45 @@ def test_dependence_radius_is_one_pixel_per_iteration(kind, rng):
         cs = slice(0 if c0 == 0 else m, (c1 - c0) if c1 == 44 else (c1 - c0) - m)
         np.testing.assert_allclose(crop[rs, cs], full[r0:r1, c0:c1][rs, cs], atol=1e-13)
         assert np.abs(crop - full[r0:r1, c0:c1]).max() > 1e-8
+
+
+# ----------------------------------------------------------------------------
+# the dual outside the support
+# ----------------------------------------------------------------------------
+
+def _dead_pixels(mask):
+    """Pixels outside the support whose lower and right neighbours (where they
+    exist) are outside it too."""
+    m = mask.astype(bool)
+    live = m.copy()
+    live[:-1, :] |= m[1:, :]
+    live[:, :-1] |= m[:, 1:]
+    return ~live
+
+
+@pytest.mark.parametrize("kind", tv.KINDS)
+@pytest.mark.parametrize("constraint", ["modulus", "none"])
+def test_dual_stays_zero_where_no_support_pixel_reaches_it(kind, constraint, rng):
+    """From q_0 = 0 (Algorithm 2, line 1) every dual group at a pixel that is
+    outside the support, and whose lower and right neighbours are outside it as
+    well, is exactly zero after any number of iterations: y = P_C(w) vanishes
+    at all three pixels that enter its difference (Eqs. 5-6), so the gradient
+    step adds nothing and P_S(0) = 0. The GPU path skips tiles made only of such
+    pixels. The group just above or left of a support pixel does move, so the
+    neighbours cannot be dropped from the rule."""
+    m, n = 23, 19
+    b = rand_img((m, n), rng, 1.3)
+    mask = np.zeros((m, n), np.uint8)
+    mask[6:15, 4:12] = 1
+    mask[m - 1, n - 1] = 1
+    mask[0, 17] = 1
+    dead = _dead_pixels(mask)
+    x, (q, _, _) = tv.fgp(b, 0.15, 37, kind, 0.5, constraint, mask, return_state=True)
+    r1, r2, s1, s2 = q
+    at = np.zeros((m, n), bool)         # any nonzero component of the group at (j, k)
+    at[:-1, :] |= (r1 != 0) | (s1 != 0)
+    at[:, :-1] |= (r2 != 0) | (s2 != 0)
+    assert not np.any(at & dead)
+    assert np.all(x[mask == 0] == 0)
+    fringe = ~dead & (mask == 0)
+    assert np.any(at & fringe)          # the groups next to the support are not zero
