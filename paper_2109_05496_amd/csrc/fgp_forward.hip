@@ -621,14 +621,18 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 // gradient step adds nothing and P_S(0) = 0; x = 0 there as well. Such pixels
 // are dead. A tile is live if its output holds a pixel that is not dead.
 //
-// live_scan_kernel: one wave per tile of one image (lane = column of the
-// output, plus one column to its right). It writes flags[tile]; with zero_st it
-// also stores zeros at the dead output pixels of both state buffers, for every
-// image of the chunk (so tiles that later launches skip read and keep zeros);
-// with x, a dead tile stores x = 0.
+// live_scan_kernel: one workgroup of kScanWaves waves per tile of one image;
+// lane = column of the output (plus one column to its right), each wave a
+// band of the output rows. It writes flags[tile]; with zero_st it also stores
+// zeros at the dead output pixels of both state buffers, for every image of
+// the chunk (so tiles that later launches skip read and keep zeros); with x, a
+// dead tile stores x = 0.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void live_scan_kernel(LiveScanArgs a) {
-  const int lane = threadIdx.x;
+constexpr int kScanWaves = 4;
+
+__global__ __launch_bounds__(kScanWaves * 64) void live_scan_kernel(LiveScanArgs a) {
+  __shared__ int sLive[kScanWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t = blockIdx.x;
   const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
   const int OW = kRW - 2 * a.halo, OH = a.rows - 2 * a.halo;
@@ -637,9 +641,11 @@ __global__ __launch_bounds__(64) void live_scan_kernel(LiveScanArgs a) {
   const bool kout = lane < OW && k < a.n;
   const long long px = (long long)a.m * a.n;
   const int jend = min(j0 + OH, a.m);  // output rows [j0, jend)
-  bool below = (kin && jend < a.m) ? (a.mask[(long long)jend * a.n + k] != 0) : false;
+  const int band = (jend - j0 + kScanWaves - 1) / kScanWaves;
+  const int jlo = j0 + wave * band, jhi = min(jend, jlo + band);
+  bool below = (kin && jhi < a.m && jhi > jlo) ? (a.mask[(long long)jhi * a.n + k] != 0) : false;
   bool live = false;
-  for (int j = jend - 1; j >= j0; --j) {
+  for (int j = jhi - 1; j >= jlo; --j) {
     const long long p = (long long)j * a.n + k;
     const bool cur = kin ? (a.mask[p] != 0) : false;
     const bool right = __shfl_down(cur ? 1 : 0, 1) != 0 && lane < 63;
@@ -659,10 +665,14 @@ __global__ __launch_bounds__(64) void live_scan_kernel(LiveScanArgs a) {
     }
     below = cur;
   }
-  const bool tile_live = __builtin_amdgcn_ballot_w64(live) != 0;
-  if (lane == 0) a.flags[t] = tile_live ? 1 : 0;
+  const bool wave_live = __builtin_amdgcn_ballot_w64(live) != 0;
+  if (lane == 0) sLive[wave] = wave_live ? 1 : 0;
+  __syncthreads();
+  bool tile_live = false;
+  for (int w = 0; w < kScanWaves; ++w) tile_live = tile_live || sLive[w] != 0;
+  if (threadIdx.x == 0) a.flags[t] = tile_live ? 1 : 0;
   if (!tile_live && a.x && kout) {
-    for (int j = j0; j < jend; ++j)
+    for (int j = jlo; j < jhi; ++j)
       for (int img = 0; img < a.batch; ++img)
         reinterpret_cast<float2*>(a.x)[(long long)img * px + (long long)j * a.n + k] = make_float2(0.0f, 0.0f);
   }
@@ -701,7 +711,7 @@ __global__ __launch_bounds__(1024) void live_list_kernel(const int* __restrict__
 hipError_t launch_live_tiles(const LiveScanArgs& a, int* live, hipStream_t s) {
   const int count = a.tiles_x * a.tiles_y;
   if (a.halo < 1 || kRW - 2 * a.halo < 1 || a.rows - 2 * a.halo < 1 || count < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(live_scan_kernel, dim3(count), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(live_scan_kernel, dim3(count), dim3(kScanWaves * 64), 0, s, a);
   hipLaunchKernelGGL(live_list_kernel, dim3(1), dim3(1024), 0, s, a.flags, count, live);
   return hipGetLastError();
 }
