@@ -4,13 +4,15 @@
 Workload (one "step"): the masked 2048 x 2048 complex64 denoising problem
 (200 random disks/rectangles, noise sigma 0.15, lambda 0.08, |x| <= 1 with a
 square support covering 70 % of the pixels), solved with 200 FGP iterations for
-each of the four complex TV kinds (type-I/II, isotropic/anisotropic). Inputs
-are synthetic and seeded, resident in HBM before timing starts.
+each of the four complex TV kinds (type-I/II, isotropic/anisotropic), the four
+solves submitted as one batched plan (one HIP graph). Inputs are synthetic and
+seeded, resident in HBM before timing starts.
 
 Prints one JSON line: Mpixel-iterations/s over the timed steps, the roofline
-record of the dominant kernel (the fused FGP tile kernel; average launch
-duration from HIP events on the stream the kernels run on), and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+record of the dominant kernel (the batched fused FGP tile kernel; average
+launch duration from HIP events on the stream the graph runs on), the same
+solves as four plain calls and with every tile run, and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
 
 Each problem runs in the launch configuration (tile shape, iterations fused
 per launch) the library's autotuner chose for it: from the saved tuning table
@@ -47,7 +49,7 @@ FLOPS_PER_PX_IT = {"1i": 52, "1a": 52, "2i": 52, "2a": 44}
 # the dual step 8, the P_S scale or clip 6 / 8 / 10 / 8, the in-place update 12.
 OPS_PER_PX_IT = {"1i": 41, "1a": 43, "2i": 45, "2a": 43}
 KIND_INDEX = {"1i": 0, "1a": 1, "2i": 2, "2a": 3}
-PMC_PROFILE = "fgp_col_kernel_2048sq_masked_4kinds_K200_pmc.md"
+PMC_PROFILE = "fgp_batched_kernel_2048sq_masked_4kinds_K200_pmc.md"
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TUNING_TABLE = os.path.join(ROOT, "paper_2109_05496_amd", "tuning", "mi355x.jsonl")
 
@@ -316,63 +318,37 @@ def live_tile_px(mask, halo, rows):
     return int(tl.sum()), int(tl.size), int((np.outer(hr, wc) * tl).sum())
 
 
-def bench_without_skip(ctv, c, torch, dev, b, mask, x, ws, run_kind, args, per_kind_ms, by_kind):
-    """The same four solves with every tile run: a warm start from an all-zero
-    dual state is the cold start's iteration, but ctv_denoise builds live-tile
-    lists only for cold starts. Results must be bitwise those of the timed run."""
+def bench_plain_calls(ctv, c, torch, dev, b, mask, x_plan, tuner, args):
+    """The same four solves as four ctv_denoise calls (each in its own tuned
+    configuration), and as the same calls with every tile run: a warm start from
+    an all-zero dual state is the cold start's iteration, but ctv_denoise builds
+    live-tile lists only for cold starts. Both must equal the plan bit for bit."""
     m, n = c["b"].shape
     K = args.iters
+    ws = torch.empty(ctv.workspace_size(m, n, 1, iters=K, fuse=args.fuse)[0], dtype=torch.uint8, device=dev)
     zero = torch.zeros((1, 2, m, n, 4), dtype=torch.float32, device=dev)
-    xd = torch.empty_like(x)
+    x = torch.empty_like(b)
     stream = torch.cuda.current_stream(dev)
-    same, dense = True, {}
-    for kind in c["kinds"]:
-        def dense_run():
-            ctv.denoise(b, c["lam"], kind=kind, alpha=c["alpha"], constraint=c["constraint"], support=mask,
-                        iters=K, fuse=args.fuse, out=xd, workspace=ws, state=zero, k0=0)
-        dense[kind] = timed(dense_run, max(1, args.steps), torch, stream)
-        run_kind(kind)
-        torch.cuda.synchronize()
-        same = same and torch.equal(xd.view(torch.float32), x.view(torch.float32))
-    T, (tw, tr) = by_kind["1i"]["fuse"], by_kind["1i"]["tile"]
-    live_tiles, all_tiles, live_px = live_tile_px(c["mask"], T, tw * tr)
-    dense_ms = sum(dense.values())
-    skip_ms = sum(per_kind_ms.values()) / args.steps
-    return {"what": "tiles whose outputs lie where the dual stays zero (outside the support, no support pixel "
-                    "below or right) are not run; every tile run instead:",
-            "live_tiles": [live_tiles, all_tiles], "computed_px_frac": round(live_px / (m * n), 4),
-            "every_tile_ms_per_step": round(dense_ms, 3),
-            "every_tile_Mpx_it_s": round(len(c["kinds"]) * m * n * K / dense_ms / 1e3, 1),
-            "speedup": round(dense_ms / skip_ms, 3), "bitwise_equal": bool(same)}
-
-
-def bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, tuner, reps=5):
-    """The same masked 2048^2 workload (four kinds x 200 iterations) submitted
-    as one ragged batched plan (one HIP graph) instead of four plain calls:
-    four times the tiles per fused step fill the 512 resident workgroups
-    better. Each image is checked bit for bit against its plain call."""
-    import numpy as np
-    m, n = c["b"].shape
-    kinds = list(c["kinds"])
-    descs = [dict(m=m, n=n, lam=c["lam"], kind=k, alpha=c["alpha"], iters=c["iters"], has_support=True)
-             for k in kinds]
-    plan = ctv.BatchedPlan(descs)
-    bp = plan.pack([c["b"]] * len(kinds), device=dev)
-    sp = plan.pack_support([c["mask"]] * len(kinds), device=dev)
-    source = tuner.batched(descs, bp, sp)
-    if source == "live":
-        plan.close()
-        plan = ctv.BatchedPlan(descs)
-    tiling = plan.tiling
-    xp = torch.empty_like(bp)
-    stream = torch.cuda.current_stream(dev)
-    ms = timed(lambda: plan.run(bp, sp, out=xp), reps, torch, stream)
-    outs = plan.unpack(xp)
-    same = all(torch.equal(outs[i].view(torch.float32), x_plain[k].view(torch.float32)) for i, k in enumerate(kinds))
-    plan.close()
-    px_it = len(kinds) * m * n * c["iters"]
-    return {"workload": f"masked {m}x{n}, four kinds x {c['iters']} iterations as one batched plan",
-            "tuning": {"fuse": tiling[0], "tile": list(tiling[1:]), "source": source}, "ms": round(ms, 3), "Mpx_it_s": round(px_it / ms / 1e3, 1), "bitwise_equal_to_plain": bool(same)}
+    reps = max(1, args.steps)
+    plain_ms, every_ms, same_plain, same_every, tuning = {}, {}, True, True, {}
+    for i, kind in enumerate(c["kinds"]):
+        kw = dict(kind=kind, alpha=c["alpha"], constraint=c["constraint"], support=mask, iters=K, fuse=args.fuse,
+                  out=x, workspace=ws)
+        source = tuner.plain(b, c["lam"], kind, c["alpha"], c["constraint"], mask, K, out=x, workspace=ws)
+        T, _, tw, tr = ctv.tiling(args.fuse, K, m, n, detail=True, kind=kind, constraint=c["constraint"])
+        tuning[kind] = {"fuse": T, "tile": [tw, tr], "source": source}
+        plain_ms[kind] = timed(lambda: ctv.denoise(b, c["lam"], **kw), reps, torch, stream)
+        same_plain = same_plain and torch.equal(x.view(torch.float32), x_plan[i].view(torch.float32))
+        every_ms[kind] = timed(lambda: ctv.denoise(b, c["lam"], state=zero, k0=0, **kw), reps, torch, stream)
+        same_every = same_every and torch.equal(x.view(torch.float32), x_plan[i].view(torch.float32))
+    px_it = len(c["kinds"]) * m * n * K
+    pm, em = sum(plain_ms.values()), sum(every_ms.values())
+    plain = {"workload": "the same four solves as four ctv_denoise calls", "tuning": tuning,
+             "ms": round(pm, 3), "per_kind_ms": {k: round(v, 3) for k, v in plain_ms.items()},
+             "Mpx_it_s": round(px_it / pm / 1e3, 1), "bitwise_equal_to_plan": bool(same_plain)}
+    every = {"workload": "the four calls with every tile run (no live-tile lists)", "ms": round(em, 3),
+             "Mpx_it_s": round(px_it / em / 1e3, 1), "bitwise_equal_to_plan": bool(same_every)}
+    return plain, every
 
 
 def bench_small(ctv, synth, torch, dev, tuner, reps=20):
@@ -441,76 +417,72 @@ def main():
     K = args.iters
     b = torch.as_tensor(c["b"]).to(dev)
     mask = torch.as_tensor(c["mask"]).to(dev)
-    x = torch.empty_like(b)
-    ws_bytes, _ = ctv.workspace_size(m, n, 1, iters=K, fuse=args.fuse)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     kinds = list(c["kinds"])
 
-    def run_kind(kind):
-        ctv.denoise(b, c["lam"], kind=kind, alpha=c["alpha"], constraint=c["constraint"], support=mask,
-                    iters=K, fuse=args.fuse, out=x, workspace=ws)
-
-    from paper_2109_05496_amd import prof_summary, tiling
+    # One step: the four solves submitted as one batched plan (one HIP graph;
+    # four images' live tiles per fused step fill the GPU far better than one).
+    from paper_2109_05496_amd import prof_summary
     tuner = Tuner(ctv, "off" if args.fuse else args.tuning, args.tuning_table)
-    by_kind = {}
-    for kind in kinds:
-        source = tuner.plain(b, c["lam"], kind, c["alpha"], c["constraint"], mask, K, out=x, workspace=ws)
-        T_k, _, tw_k, tr_k = tiling(args.fuse, K, m, n, detail=True, kind=kind, constraint=c["constraint"])
-        by_kind[kind] = {"fuse": T_k, "tile": [tw_k, tr_k], "source": source}
+    descs = [dict(m=m, n=n, lam=c["lam"], kind=k, alpha=c["alpha"], iters=K, has_support=True) for k in kinds]
+    plan = ctv.BatchedPlan(descs, constraint=c["constraint"], fuse=args.fuse)
+    bp = plan.pack([c["b"]] * len(kinds), device=dev)
+    sp = plan.pack_support([c["mask"]] * len(kinds), device=dev)
+    source = tuner.batched(descs, bp, sp) if not args.fuse else "fixed"
+    if source == "live":
+        plan.close()
+        plan = ctv.BatchedPlan(descs, constraint=c["constraint"], fuse=args.fuse)
+    T, tw, tr = plan.tiling
+    launch_cfg = {"four_kinds_plan": {"fuse": T, "tile": [tw, tr], "source": source}}
+    xp = torch.empty_like(bp)
+
+    def step():
+        plan.run(bp, sp, out=xp)
 
     for _ in range(args.warmup):
-        for kind in kinds:
-            run_kind(kind)
+        step()
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream(dev)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(kinds) + 1)] for _ in range(args.steps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
+    ev[0].record(stream)
     for s in range(args.steps):
-        ev[s][0].record(stream)
-        for i, kind in enumerate(kinds):
-            run_kind(kind)
-            ev[s][i + 1].record(stream)
+        step()
+        ev[s + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_kind_ms = {k: 0.0 for k in kinds}
-    for s in range(args.steps):
-        for i, kind in enumerate(kinds):
-            per_kind_ms[kind] += ev[s][i].elapsed_time(ev[s][i + 1])
-    gpu_ms = sum(per_kind_ms.values())
-    ms_per_step = gpu_ms / args.steps
+    step_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(args.steps)]
+    ms_per_step = sum(step_ms) / args.steps
     px_iters_step = len(kinds) * m * n * K
     value = px_iters_step / (ms_per_step * 1e-3) / 1e6
 
-    # Roofline of the dominant kernel: the fused tile kernel (one instantiation
-    # per TV kind; every launch in the timed region is one of them, so the
-    # average launch duration is the kind's event time over its launch count,
-    # which also holds the two small live-tile scans of the call). The work of
-    # a launch is what it computes: the output pixels of the live tiles (tiles
-    # outside the support are not run) times its fused iterations.
-    dom = max(kinds, key=lambda k: per_kind_ms[k])
-    T, (tw, tr) = by_kind[dom]["fuse"], by_kind[dom]["tile"]
+    # Roofline of the dominant kernel, the batched fused tile kernel: every
+    # launch of a step is one of its ceil(K / T) graph nodes (plus one small scan
+    # and one list node, whose time the event average also holds). The work of
+    # a launch is what it computes: the output pixels of the live tiles of the
+    # four images (tiles outside the support are not run) times T.
     launches = math.ceil(K / T)
-    kname = f"void ctv::fgp_col_kernel<{KIND_INDEX[dom]}, 1, true, {tw}, {tr}, false>(ctv::FgpPlainArgs)"
-    avg_launch_s = per_kind_ms[dom] / args.steps / launches * 1e-3
+    kname = f"void ctv::fgp_batched_kernel<1, {tw}, {tr}>(ctv::FgpBatchedArgs)"
+    avg_launch_s = ms_per_step / launches * 1e-3
     live_tiles, all_tiles, live_px = live_tile_px(c["mask"], T, tw * tr)
-    run_px_it = live_px * K               # computed pixel-iterations of one kind
-    alg_bytes_launch = BYTES_PER_PX_IT_MASKED * run_px_it / launches
-    alg_flops_launch = FLOPS_PER_PX_IT[dom] * run_px_it / launches
-    alg_ops_launch = OPS_PER_PX_IT[dom] * run_px_it / launches
+    run_px_it = live_px * K                   # computed pixel-iterations of one kind
+    alg_bytes_launch = BYTES_PER_PX_IT_MASKED * run_px_it * len(kinds) / launches
+    alg_flops_launch = sum(FLOPS_PER_PX_IT[k] for k in kinds) * run_px_it / launches
+    alg_ops_launch = sum(OPS_PER_PX_IT[k] for k in kinds) * run_px_it / launches
     achieved_gbs = alg_bytes_launch / avg_launch_s / 1e9
     achieved_tflops = alg_flops_launch / avg_launch_s / 1e12
     achieved_gops = alg_ops_launch / avg_launch_s / 1e9
     pmc = prof_summary.load_pmc(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", PMC_PROFILE))
     # the profile counts only while it was taken with the same launch configuration
-    same_config = bool(pmc) and pmc.get("tuning") == prof_summary.tuning_signature(by_kind)
+    same_config = bool(pmc) and pmc.get("tuning") == prof_summary.tuning_signature(launch_cfg)
     kp = pmc["kernels"].get(kname) if (same_config and args.size == 2048 and K == 200 and args.fuse == 0) else None
     roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": round(VALU_OPS_PEAK_GOPS, 1),
             "unit": "Gop/s", "frac": round(achieved_gops / VALU_OPS_PEAK_GOPS, 4),
             "traffic": kp["traffic_bytes"] if kp else None,
             "kernel": kname, "fused_iters": T, "avg_launch_us": round(avg_launch_s * 1e6, 2),
             "alg_ops_per_launch": int(alg_ops_launch),
-            "live_tiles": [live_tiles, all_tiles], "computed_px_frac": round(live_px / (m * n), 4),
+            "live_tiles": [len(kinds) * live_tiles, len(kinds) * all_tiles],
+            "computed_px_frac": round(live_px / (m * n), 4),
             "fp32_flops": {"achieved": round(achieved_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
                            "alg_flops_per_launch": int(alg_flops_launch)},
@@ -524,24 +496,19 @@ def main():
            "unit": "Mpixel-iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"masked {m}x{n} complex64 CTV denoise, all four TV kinds x {K} FGP iterations",
+           "config": {"workload": f"masked {m}x{n} complex64 CTV denoise, all four TV kinds x {K} FGP iterations, "
+                                  "submitted as one batched plan (one HIP graph)",
                       "size": [m, n], "kinds": kinds, "iters": K, "lambda": c["lam"], "alpha": c["alpha"],
                       "constraint": "|x|<=1 + 70% square support",
                       "tiles": "live only: tiles whose output lies where the dual stays zero are not run "
                                "(results bitwise those of running every tile)"},
-           "tuning": {"mode": tuner.mode, "table": tuner.table, "by_kind": by_kind},
-           "per_kind_ms": {k: round(v / args.steps, 3) for k, v in per_kind_ms.items()},
+           "tuning": {"mode": tuner.mode, "table": tuner.table, "launch": launch_cfg},
            "wall_s": round(wall, 3),
            "roofline": roof}
     if not args.no_extras:
-        out["dead_tile_skip"] = bench_without_skip(ctv, c, torch, dev, b, mask, x, ws, run_kind, args, per_kind_ms,
-                                                   by_kind)
-        if args.size == 2048 and K == 200:
-            x_plain = {}
-            for kind in kinds:
-                run_kind(kind)
-                x_plain[kind] = x.clone()
-            out["four_kinds_one_plan"] = bench_four_kinds_one_plan(ctv, c, torch, dev, x_plain, tuner)
+        x_plan = [t.reshape(m, n) for t in plan.unpack(xp)]
+        out["four_plain_calls"], out["every_tile"] = bench_plain_calls(ctv, c, torch, dev, b, mask, x_plan, tuner,
+                                                                       args)
         out["small_64"] = bench_small(ctv, synth, torch, dev, tuner)
         out["out_of_cache_8192"] = bench_out_of_cache(ctv, synth, torch, dev, tuner)
         out["batched"] = bench_batched(ctv, synth, torch, dev, tuner)

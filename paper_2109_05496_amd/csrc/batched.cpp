@@ -9,7 +9,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <numeric>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -36,6 +38,19 @@ struct ctv_batched_plan {
   hipGraphExec_t exec = nullptr;
   const void* func = nullptr;
   int block = 0;
+  // live-tile skipping for images with a support (see ctv_denoise): scan and
+  // compaction nodes ahead of the steps
+  int nflags = 0;
+  BatchGeom* d_geoms = nullptr;
+  int* d_geo_of = nullptr;
+  int* d_flags = nullptr;
+  int* d_lists = nullptr;
+  int* d_counts = nullptr;
+  int* d_step_offset = nullptr;
+  int* d_step_count = nullptr;
+  BatchScanArgs scan_args{};
+  BatchCompactArgs compact_args{};
+  hipGraphNode_t scan_node = nullptr, compact_node = nullptr;
   const float* b = nullptr;
   const uint8_t* support = nullptr;
   float* x = nullptr;
@@ -51,6 +66,9 @@ void release(ctv_batched_plan* p) {
   if (p->d_images) (void)hipFree(p->d_images);
   if (p->d_tiles) (void)hipFree(p->d_tiles);
   if (p->d_beta) (void)hipFree(p->d_beta);
+  for (void* q : {(void*)p->d_geoms, (void*)p->d_geo_of, (void*)p->d_flags, (void*)p->d_lists, (void*)p->d_counts,
+                  (void*)p->d_step_offset, (void*)p->d_step_count})
+    if (q) (void)hipFree(q);
   delete p;
 }
 
@@ -72,7 +90,36 @@ void fill_args(ctv_batched_plan* p) {
     a.x = p->x;
     a.k0 = (int)s * p->tiling.T;
     a.T = p->tiling.T;
+    a.live = p->nflags ? p->d_lists + p->step_offset[s] : nullptr;
+    a.live_count = p->nflags ? p->d_counts + s : nullptr;
   }
+  BatchScanArgs& sa = p->scan_args;
+  sa.images = p->d_images;
+  sa.geoms = p->d_geoms;
+  sa.geo_of = p->d_geo_of;
+  sa.support = p->support;
+  sa.st0 = buf0;
+  sa.st1 = buf1;
+  sa.x = p->x;
+  sa.flags = p->d_flags;
+  sa.rows = p->tiling.shape.rows();
+  BatchCompactArgs& ca = p->compact_args;
+  ca.tiles = p->d_tiles;
+  ca.step_offset = p->d_step_offset;
+  ca.step_count = p->d_step_count;
+  ca.flags = p->d_flags;
+  ca.lists = p->d_lists;
+  ca.counts = p->d_counts;
+}
+
+hipKernelNodeParams aux_params(const void* func, int grid, int block, void** kp) {
+  hipKernelNodeParams np;
+  std::memset(&np, 0, sizeof(np));
+  np.func = const_cast<void*>(func);
+  np.gridDim = dim3((unsigned)grid);
+  np.blockDim = dim3((unsigned)block);
+  np.kernelParams = kp;
+  return np;
 }
 
 hipKernelNodeParams node_params(ctv_batched_plan* p, size_t s, void** kp) {
@@ -91,10 +138,21 @@ ctv_status build_graph(ctv_batched_plan* p) {
   hipError_t e = hipGraphCreate(&p->graph, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
   p->nodes.assign(p->args.size(), nullptr);
+  if (p->nflags) {
+    void* kp0[] = {&p->scan_args};
+    hipKernelNodeParams n0 = aux_params(batched_scan_kernel_ptr(), p->nflags, 256, kp0);
+    e = hipGraphAddKernelNode(&p->scan_node, p->graph, nullptr, 0, &n0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (live scan)");
+    void* kp1[] = {&p->compact_args};
+    hipKernelNodeParams n1 = aux_params(batched_compact_kernel_ptr(), (int)p->args.size(), 1024, kp1);
+    e = hipGraphAddKernelNode(&p->compact_node, p->graph, &p->scan_node, 1, &n1);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (live lists)");
+  }
   for (size_t s = 0; s < p->args.size(); ++s) {
     void* kp[] = {&p->args[s]};
     hipKernelNodeParams np = node_params(p, s, kp);
-    e = hipGraphAddKernelNode(&p->nodes[s], p->graph, s ? &p->nodes[s - 1] : nullptr, s ? 1 : 0, &np);
+    const hipGraphNode_t* dep = s ? &p->nodes[s - 1] : (p->nflags ? &p->compact_node : nullptr);
+    e = hipGraphAddKernelNode(&p->nodes[s], p->graph, dep, dep ? 1 : 0, &np);
     if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode");
   }
   e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
@@ -177,9 +235,14 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
   const int T = tl.T;
   const int rows = tl.shape.rows();
 
-  // per-step tile lists
+  // per-step tile lists; tiles of images with a support (and iterations) get a
+  // live flag of their (image, tiling) pair
   const int steps = std::max(1, (kmax + T - 1) / T);
   std::vector<BatchTile> tiles;
+  std::vector<BatchGeom> geoms;
+  std::vector<int> geo_of;
+  std::map<std::tuple<int, int, int>, int> geo_index;
+  std::vector<char> image_zeroed((size_t)count, 0);
   for (int s = 0; s < steps; ++s) {
     const int k0 = s * T;
     p->step_offset.push_back((int)tiles.size());
@@ -191,8 +254,28 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
       const int H = std::max(1, Ti + (last ? 1 : 0));
       const int ow = 64 - 2 * H, oh = rows - 2 * H;
       const int tx = (b.n + ow - 1) / ow, ty = (b.m + oh - 1) / oh;
+      int base = -1;
+      if (b.support_offset >= 0 && b.iters > 0) {
+        const auto key = std::make_tuple(i, H, last ? 1 : 0);
+        auto it = geo_index.find(key);
+        if (it == geo_index.end()) {
+          BatchGeom g{};
+          g.image = i;
+          g.halo = H;
+          g.tiles_x = tx;
+          g.tiles_y = ty;
+          g.flag_base = (int)geo_of.size();
+          g.zero_st = image_zeroed[(size_t)i] ? 0 : 1;
+          g.zero_x = last ? 1 : 0;
+          image_zeroed[(size_t)i] = 1;
+          geo_of.insert(geo_of.end(), (size_t)tx * ty, (int)geoms.size());
+          it = geo_index.emplace(key, (int)geoms.size()).first;
+          geoms.push_back(g);
+        }
+        base = geoms[(size_t)it->second].flag_base;
+      }
       for (int y = 0; y < ty; ++y)
-        for (int x = 0; x < tx; ++x) tiles.push_back(BatchTile{i, x, y, 0});
+        for (int x = 0; x < tx; ++x) tiles.push_back(BatchTile{i, x, y, base < 0 ? -1 : base + y * tx + x});
     }
     p->step_count.push_back((int)tiles.size() - p->step_offset.back());
   }
@@ -210,6 +293,24 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_beta, beta.data(), beta.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !geoms.empty()) {
+    p->nflags = (int)geo_of.size();
+    const size_t nt = std::max<size_t>(1, tiles.size());
+    e = hipMalloc(&p->d_geoms, geoms.size() * sizeof(BatchGeom));
+    if (e == hipSuccess) e = hipMalloc(&p->d_geo_of, geo_of.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_flags, geo_of.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_lists, nt * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_counts, (size_t)steps * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_step_offset, (size_t)steps * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_step_count, (size_t)steps * sizeof(int));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_geoms, geoms.data(), geoms.size() * sizeof(BatchGeom), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_geo_of, geo_of.data(), geo_of.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_step_offset, p->step_offset.data(), (size_t)steps * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_step_count, p->step_count.data(), (size_t)steps * sizeof(int), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     release(p);
     return hip_fail(e, "batched plan setup");
@@ -244,6 +345,12 @@ ctv_status ctv_denoise_batched(ctv_batched_plan* p, const float* b, const uint8_
     if (st) return st;
   } else if (changed) {
     fill_args(p);
+    if (p->nflags) {
+      void* kp0[] = {&p->scan_args};
+      hipKernelNodeParams n0 = aux_params(batched_scan_kernel_ptr(), p->nflags, 256, kp0);
+      hipError_t e = hipGraphExecKernelNodeSetParams(p->exec, p->scan_node, &n0);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphExecKernelNodeSetParams (live scan)");
+    }
     for (size_t s = 0; s < p->args.size(); ++s) {
       void* kp[] = {&p->args[s]};
       hipKernelNodeParams np = node_params(p, s, kp);

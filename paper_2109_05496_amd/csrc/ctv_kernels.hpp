@@ -90,8 +90,41 @@ struct BatchImage {
 };
 
 struct BatchTile {
-  int image, tx, ty, pad;
+  int image, tx, ty;
+  int flag;                  // index of the tile's live flag, or -1 (image without a support: always runs)
 };
+
+// One (image, tiling) pair of a batched plan whose tiles are scanned for
+// liveness (images with a support): flags [flag_base, flag_base + tiles_x *
+// tiles_y). zero_st: this scan stores zeros at the image's dead pixels in both
+// state buffers (one pair per image); zero_x: it stores x = 0 in dead tiles
+// (the tiling of the image's last step).
+struct BatchGeom {
+  int image, halo, tiles_x, tiles_y, flag_base, zero_st, zero_x, pad;
+};
+
+struct BatchScanArgs {
+  const BatchImage* images;
+  const BatchGeom* geoms;
+  const int* geo_of;        // [nflags] the pair each flag belongs to
+  const uint8_t* support;
+  float* st0;               // the two packed state buffers
+  float* st1;
+  float* x;
+  int* flags;
+  int rows;                 // region rows of the tile shape
+};
+
+struct BatchCompactArgs {
+  const BatchTile* tiles;   // every step's tiles
+  const int* step_offset;   // [steps]
+  const int* step_count;    // [steps]
+  const int* flags;
+  int* lists;               // same indexing as tiles: step s's list at lists[step_offset[s]]
+  int* counts;              // [steps]
+};
+const void* batched_scan_kernel_ptr();
+const void* batched_compact_kernel_ptr();
 
 struct FgpBatchedArgs {
   const BatchTile* tiles;   // this step's tiles
@@ -105,6 +138,8 @@ struct FgpBatchedArgs {
   float* x;
   int k0;                   // iterations completed before this step
   int T;                    // iterations fused in this step
+  const int* live;          // this step's tiles to run (indices into tiles) or nullptr = all
+  const int* live_count;
 };
 
 // Tile shape of the plain kernels: waves > 0 selects the column-register tile

@@ -571,10 +571,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int G = gridDim.x;
   const int xcd = blockIdx.x % kXcd, bi = blockIdx.x / kXcd;
   const int gx = G / kXcd + (xcd < G % kXcd ? 1 : 0);
-  const int lo = (int)((long long)A.ntiles * xcd / kXcd);
-  const int hi = (int)((long long)A.ntiles * (xcd + 1) / kXcd);
+  const int nrun = A.live ? A.live_count[0] : A.ntiles;
+  const int lo = (int)((long long)nrun * xcd / kXcd);
+  const int hi = (int)((long long)nrun * (xcd + 1) / kXcd);
   for (int t = lo + bi; t < hi; t += gx) {
-    const BatchTile bt = A.tiles[t];
+    const BatchTile bt = A.tiles[A.live ? A.live[t] : t];
     const BatchImage D = A.images[bt.image];
     const int Ti = min(A.T, D.iters - A.k0);
     const bool last = (A.k0 + Ti == D.iters);
@@ -630,36 +631,38 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 // ---------------------------------------------------------------------------
 constexpr int kScanWaves = 4;
 
-__global__ __launch_bounds__(kScanWaves * 64) void live_scan_kernel(LiveScanArgs a) {
-  __shared__ int sLive[kScanWaves];
+// Tile t of one image's tiling (halo, rows, tiles_x): returns whether it is
+// live (the same value in every thread). st0 / st1 / x are image bases with
+// `batch` images of stride 2 m n float4 / m n float2 (zeroed as described).
+__device__ bool scan_tile(const uint8_t* __restrict__ mask, int m, int n, int halo, int rows, int tiles_x, int t,
+                          bool zero_st, float* st0, float* st1, float* x, int batch, int* sLive) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int t = blockIdx.x;
-  const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
-  const int OW = kRW - 2 * a.halo, OH = a.rows - 2 * a.halo;
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  const int OW = kRW - 2 * halo, OH = rows - 2 * halo;
   const int j0 = ty * OH, k = tx * OW + lane;
-  const bool kin = lane <= OW && k < a.n;
-  const bool kout = lane < OW && k < a.n;
-  const long long px = (long long)a.m * a.n;
-  const int jend = min(j0 + OH, a.m);  // output rows [j0, jend)
+  const bool kin = lane <= OW && k < n;
+  const bool kout = lane < OW && k < n;
+  const long long px = (long long)m * n;
+  const int jend = min(j0 + OH, m);  // output rows [j0, jend)
   const int band = (jend - j0 + kScanWaves - 1) / kScanWaves;
   const int jlo = j0 + wave * band, jhi = min(jend, jlo + band);
-  bool below = (kin && jhi < a.m && jhi > jlo) ? (a.mask[(long long)jhi * a.n + k] != 0) : false;
+  bool below = (kin && jhi < m && jhi > jlo) ? (mask[(long long)jhi * n + k] != 0) : false;
   bool live = false;
   for (int j = jhi - 1; j >= jlo; --j) {
-    const long long p = (long long)j * a.n + k;
-    const bool cur = kin ? (a.mask[p] != 0) : false;
+    const long long p = (long long)j * n + k;
+    const bool cur = kin ? (mask[p] != 0) : false;
     const bool right = __shfl_down(cur ? 1 : 0, 1) != 0 && lane < 63;
     const bool dead = !cur && !below && !right;
     if (kout) {
       live = live || !dead;
-      if (a.zero_st && dead) {
+      if (zero_st && dead) {
         const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int img = 0; img < a.batch; ++img) {
+        for (int img = 0; img < batch; ++img) {
           const long long base = (long long)img * 2 * px;
-          reinterpret_cast<float4*>(a.st0)[base + p] = z;
-          reinterpret_cast<float4*>(a.st0)[base + px + p] = z;
-          reinterpret_cast<float4*>(a.st1)[base + p] = z;
-          reinterpret_cast<float4*>(a.st1)[base + px + p] = z;
+          reinterpret_cast<float4*>(st0)[base + p] = z;
+          reinterpret_cast<float4*>(st0)[base + px + p] = z;
+          reinterpret_cast<float4*>(st1)[base + p] = z;
+          reinterpret_cast<float4*>(st1)[base + px + p] = z;
         }
       }
     }
@@ -670,13 +673,70 @@ __global__ __launch_bounds__(kScanWaves * 64) void live_scan_kernel(LiveScanArgs
   __syncthreads();
   bool tile_live = false;
   for (int w = 0; w < kScanWaves; ++w) tile_live = tile_live || sLive[w] != 0;
-  if (threadIdx.x == 0) a.flags[t] = tile_live ? 1 : 0;
-  if (!tile_live && a.x && kout) {
+  if (!tile_live && x && kout) {
     for (int j = jlo; j < jhi; ++j)
-      for (int img = 0; img < a.batch; ++img)
-        reinterpret_cast<float2*>(a.x)[(long long)img * px + (long long)j * a.n + k] = make_float2(0.0f, 0.0f);
+      for (int img = 0; img < batch; ++img)
+        reinterpret_cast<float2*>(x)[(long long)img * px + (long long)j * n + k] = make_float2(0.0f, 0.0f);
   }
+  return tile_live;
 }
+
+__global__ __launch_bounds__(kScanWaves * 64) void live_scan_kernel(LiveScanArgs a) {
+  __shared__ int sLive[kScanWaves];
+  const bool live = scan_tile(a.mask, a.m, a.n, a.halo, a.rows, a.tiles_x, blockIdx.x, a.zero_st != 0, a.st0,
+                              a.st1, a.x, a.batch, sLive);
+  if (threadIdx.x == 0) a.flags[blockIdx.x] = live ? 1 : 0;
+}
+
+// Batched plans: one workgroup per tile of every (image, tiling) pair that the
+// plan's steps use for images with a support (geo_of names the pair).
+__global__ __launch_bounds__(kScanWaves * 64) void batched_scan_kernel(BatchScanArgs a) {
+  __shared__ int sLive[kScanWaves];
+  const int f = blockIdx.x;
+  const BatchGeom G = a.geoms[a.geo_of[f]];
+  const BatchImage D = a.images[G.image];
+  const long long st = 2 * D.offset * 4;  // float offset of the image's state
+  const bool live = scan_tile(a.support + D.support_offset, D.m, D.n, G.halo, a.rows, G.tiles_x,
+                              f - G.flag_base, G.zero_st != 0, a.st0 + st, a.st1 + st,
+                              G.zero_x ? a.x + 2 * D.offset : nullptr, 1, sLive);
+  if (threadIdx.x == 0) a.flags[f] = live ? 1 : 0;
+}
+
+// Batched plans: one workgroup per step lists the step's tiles that run (tiles
+// of images without a support always run; the others by their flag), in
+// order, at lists[step_offset] with the count in counts[step].
+__global__ __launch_bounds__(1024) void batched_compact_kernel(BatchCompactArgs a) {
+  __shared__ int sWave[16];
+  const int s = blockIdx.x;
+  const BatchTile* tiles = a.tiles + a.step_offset[s];
+  const int count = a.step_count[s];
+  int* list = a.lists + a.step_offset[s];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (count + 1023) / 1024;
+  const int lo = min(count, tid * per), hi = min(count, lo + per);
+  int own = 0;
+  for (int i = lo; i < hi; ++i) own += (tiles[i].flag < 0 || a.flags[tiles[i].flag] != 0) ? 1 : 0;
+  int inc = own;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(inc, d);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) sWave[wave] = inc;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int w = 0; w < 16; ++w) {
+    const int v = sWave[w];
+    before += (w < wave) ? v : 0;
+    total += v;
+  }
+  if (tid == 0) a.counts[s] = total;
+  int pos = before + inc - own;
+  for (int i = lo; i < hi; ++i)
+    if (tiles[i].flag < 0 || a.flags[tiles[i].flag] != 0) list[pos++] = i;
+}
+
+const void* batched_scan_kernel_ptr() { return reinterpret_cast<const void*>(&batched_scan_kernel); }
+const void* batched_compact_kernel_ptr() { return reinterpret_cast<const void*>(&batched_compact_kernel); }
 
 // One workgroup: live[0] = number of live tiles, live[1 ..] = their indices in
 // increasing order (each thread takes a contiguous run of flags; a block-wide

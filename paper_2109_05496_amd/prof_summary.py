@@ -18,7 +18,7 @@ import json
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/fgp_forward.hip", "csrc/ctv_device.hpp", "csrc/capi.cpp")
+KERNEL_SOURCES = ("csrc/fgp_forward.hip", "csrc/ctv_device.hpp", "csrc/capi.cpp", "csrc/batched.cpp")
 
 
 def kernel_source_hash():
@@ -65,7 +65,7 @@ def stats(csv_path, out, cmd, match=None, title=None):
 
 
 def tuning_signature(by_kind):
-    """{kind: [fuse, tile_waves, tile_rows]} of a benchmark's launch configuration."""
+    """{problem: [fuse, tile_waves, tile_rows]} of a benchmark's launch configuration."""
     return {k: [int(v["fuse"])] + [int(t) for t in v["tile"]] for k, v in sorted(by_kind.items())}
 
 
@@ -73,11 +73,12 @@ def bench_tuning(log_path):
     """Launch configuration recorded in the JSON line a bench.py run printed."""
     for line in reversed(open(log_path).read().splitlines()):
         if line.startswith("{"):
-            return tuning_signature(json.loads(line)["tuning"]["by_kind"])
+            return tuning_signature(json.loads(line)["tuning"]["launch"])
     raise ValueError(f"no bench.py result line in {log_path}")
 
 
-def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, kernel_prefix="void ctv::fgp_col_kernel",
+def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30,
+        kernel_prefix=("void ctv::fgp_col_kernel", "void ctv::fgp_batched_kernel"),
         bench_log=None):
     fetch, write, valu = _counters(fetch_dir), _counters(write_dir), _counters(valu_dir)
     copy = next(k for k in fetch if "copyBuffer" in k)

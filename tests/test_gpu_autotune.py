@@ -150,3 +150,31 @@ def test_benchmark_configuration_at_full_size_equals_default():
         x_bench = ctv().denoise(bt, c["lam"], fuse=fuse, tile=tile, **args)
         torch.cuda.synchronize()
         assert torch.equal(f32(x_bench), f32(x_default)), (kind, fuse, tile)
+
+
+def test_benchmark_plan_at_full_size_equals_plain_calls():
+    """The benchmark's step: the masked 2048^2 four-kind workload as one batched
+    plan in the saved table's configuration (live tiles only). Every image
+    equals the default plain call bit for bit, which the corner-crop test pins
+    to the oracle."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2109_05496_amd",
+                        "tuning", "mi355x.jsonl")
+    c = synth.config2(0)
+    m, n = c["b"].shape
+    descs = [dict(m=m, n=n, lam=c["lam"], kind=k, alpha=c["alpha"], iters=c["iters"], has_support=True)
+             for k in c["kinds"]]
+    ctv().tune_cache_clear()
+    ctv().tune_cache_load(path)
+    try:
+        assert ctv().batched_tuned(descs) is not None
+        plan = ctv().BatchedPlan(descs)
+        out = plan.unpack(plan.run(plan.pack([c["b"]] * 4), plan.pack_support([c["mask"]] * 4)))
+        bt, mt = torch.as_tensor(c["b"]).cuda(), torch.as_tensor(c["mask"]).cuda()
+        for i, kind in enumerate(c["kinds"]):
+            ref = ctv().denoise(bt, c["lam"], kind=kind, alpha=c["alpha"], support=mt, iters=c["iters"], fuse=8,
+                                tile=(8, 8))
+            assert torch.equal(f32(out[i].reshape(m, n)), f32(ref)), kind
+        plan.close()
+    finally:
+        ctv().tune_cache_clear()
