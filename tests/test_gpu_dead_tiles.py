@@ -152,18 +152,22 @@ def test_batched_plan_skips_dead_tiles_bitwise():
     """A batched plan runs only the live tiles of its images with a support
     (scan and list nodes ahead of the steps): every image equals the plain call
     that runs every tile, for ragged sizes and iteration counts, lambda = 0 and
-    K = 0 images with a support, images without one, and a NaN-filled workspace;
-    a second run with new buffers patches the scan node."""
+    K = 0 images with a support, empty and full supports, images without one,
+    and a NaN-filled workspace; a second run with new buffers patches the scan
+    node."""
     rng = np.random.default_rng(46)
-    specs = [(300, 420, "1i", 0.07, 37, True), (150, 230, "2a", 0.1, 12, True), (90, 70, "1a", 0.05, 20, False),
-             (200, 260, "2i", 0.0, 15, True), (130, 190, "1i", 0.08, 0, True), (64, 64, "1a", 0.06, 9, True)]
+    specs = [(300, 420, "1i", 0.07, 37, "sparse"), (150, 230, "2a", 0.1, 12, "sparse"), (90, 70, "1a", 0.05, 20, None),
+             (200, 260, "2i", 0.0, 15, "sparse"), (130, 190, "1i", 0.08, 0, "sparse"), (64, 64, "1a", 0.06, 9, "sparse"),
+             (80, 120, "2i", 0.09, 14, "empty"), (100, 100, "1a", 0.05, 21, "full")]
     imgs, bs, masks = [], [], []
-    for m, n, kind, lam, K, has in specs:
+    for m, n, kind, lam, K, sup in specs:
         _, b = synth.denoise_case(m, n, 6, 0.15, rng)
         bs.append(b)
-        imgs.append(dict(m=m, n=n, lam=lam, kind=kind, alpha=0.5, iters=K, has_support=has))
-        if has:
+        imgs.append(dict(m=m, n=n, lam=lam, kind=kind, alpha=0.5, iters=K, has_support=sup is not None))
+        if sup == "sparse":
             masks.append(sparse_mask(m, n))
+        elif sup is not None:
+            masks.append((np.ones if sup == "full" else np.zeros)((m, n), np.uint8))
     plan = ctv().BatchedPlan(imgs)
     bp, sp = plan.pack(bs), plan.pack_support(masks)
     plan._ws = torch.full((max(plan.ws_bytes, 1),), 0xFF, dtype=torch.uint8, device="cuda")
