@@ -145,6 +145,12 @@ ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, 
  *               ctv_denoise_backward; requires state_in == NULL.
  *   saved       [ceil(K/c) - 1][batch][2][m][n][4] floats, or NULL when no slot is needed.
  *   ws          workspace of at least ctv_workspace_size() bytes.
+ * With a support and a cold start, the dual stays exactly zero at pixels that
+ * are outside the support and have no support pixel below or to the right
+ * (from q_0 = 0, y vanishes at every pixel their differences read), and x = 0
+ * there: tiles made only of such pixels are not computed (results are bitwise
+ * those of computing them, for finite b). The call then launches two small
+ * kernels per tiling that list the other tiles.
  * Errors: CTV_ERR_INVALID_ARG (null/negative/out-of-range arguments, unknown
  * kind/constraint, alpha outside [0,1], lambda < 0 or non-finite, m or n < 1,
  * struct_size mismatch), CTV_ERR_WORKSPACE (ws_bytes too small),
@@ -181,7 +187,9 @@ ctv_status ctv_batched_workspace_size(const ctv_batched_plan* plan, size_t* ws_b
 /* Runs the plan: b_packed and x_packed are complex64 buffers addressed by the
  * descriptors' offsets; support_packed is a uint8 buffer (NULL if no image has
  * a mask). One graph launch on `stream`; kernel arguments are refreshed when
- * the pointers change between calls. */
+ * the pointers change between calls. As in ctv_denoise, the tiles of images
+ * with a support whose pixels all keep a zero dual are not computed (two
+ * graph nodes ahead of the steps list the others). */
 ctv_status ctv_denoise_batched(ctv_batched_plan* plan, const float* b_packed,
                                const uint8_t* support_packed, float* x_packed, void* ws,
                                size_t ws_bytes, ctv_stream_t stream);
