@@ -182,3 +182,47 @@ def test_batched_plan_skips_dead_tiles_bitwise():
         assert np.array_equal(bits(out1[i]), bits(ref)), i
         assert np.array_equal(bits(out2[i]), bits(ref)), i
     plan.close()
+
+
+def blob_mask(m, n, rng):
+    """A few random rectangles and single pixels (possibly none) on an empty
+    support: every kind of live/dead tile neighbourhood."""
+    mk = np.zeros((m, n), np.uint8)
+    for _ in range(int(rng.integers(0, 4))):
+        j0, k0 = int(rng.integers(0, m)), int(rng.integers(0, n))
+        mk[j0:j0 + int(rng.integers(1, max(2, m // 3))), k0:k0 + int(rng.integers(1, max(2, n // 3)))] = 1
+    for _ in range(int(rng.integers(0, 3))):
+        mk[int(rng.integers(0, m)), int(rng.integers(0, n))] = 1
+    return mk
+
+
+def test_random_supports_plain_and_batched():
+    """Twenty seeded random problems (sizes 1..300 per side, random supports,
+    kinds, tile shapes, fusion depths and K): plain calls equal their every-tile
+    runs, and one batched plan of all of them equals the plain calls."""
+    rng = np.random.default_rng(47)
+    shapes = [(8, 8), (8, 4), (4, 8), (16, 4), (16, 8)]
+    imgs, bs, masks, outs = [], [], [], []
+    for case in range(20):
+        m, n = int(rng.integers(1, 301)), int(rng.integers(1, 301))
+        kind = str(rng.choice(["1i", "1a", "2i", "2a"]))
+        K = int(rng.integers(1, 30))
+        fuse = int(rng.integers(1, 10))
+        tile = shapes[int(rng.integers(0, len(shapes)))]
+        b = (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))).astype(np.complex64)
+        mk = blob_mask(m, n, rng)
+        bt, mt = dev(b), dev(mk)
+        x = ctv().denoise(bt, 0.1, kind=kind, support=mt, iters=K, fuse=fuse, tile=tile)
+        xd = ctv().denoise(bt, 0.1, kind=kind, support=mt, iters=K, fuse=fuse, tile=tile,
+                           state=zero_state(1, m, n), k0=0)
+        assert np.array_equal(bits(x), bits(xd)), (case, m, n, kind, K, fuse, tile)
+        imgs.append(dict(m=m, n=n, lam=0.1, kind=kind, alpha=0.5, iters=K, has_support=True))
+        bs.append(b)
+        masks.append(mk)
+        outs.append(x)
+    plan = ctv().BatchedPlan(imgs)
+    got = plan.unpack(plan.run(plan.pack(bs), plan.pack_support(masks)))
+    for i, x in enumerate(outs):
+        ref = ctv().denoise(dev(bs[i]), 0.1, kind=imgs[i]["kind"], support=dev(masks[i]), iters=imgs[i]["iters"])
+        assert np.array_equal(bits(got[i]), bits(ref)), i
+    plan.close()
