@@ -118,7 +118,8 @@ def test_checkpoints_with_skipping_equal_resumed_states(kind):
 def test_tilings_chunks_and_single_launch():
     """K = 50 with T = 8 runs launches of 8 and 7 iterations and an x launch
     (three tilings, three lists); K = 5 is one launch that writes x; 33 images
-    are two chunks of the batch, each with its own lists."""
+    are two chunks of the batch, each with its own lists. The duality gap and
+    the returned state match too."""
     m, n = 150, 230
     rng = np.random.default_rng(44)
     mk = dev(sparse_mask(m, n))
@@ -127,9 +128,15 @@ def test_tilings_chunks_and_single_launch():
         bt = dev(bs)
         lams = list(np.linspace(0.04, 0.12, B))
         ws = nan_workspace(m, n, B, "1a", iters, 8)
-        x = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8, workspace=ws)
-        xd = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8, state=zero_state(B, m, n), k0=0)
+        x, g = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8, workspace=ws, gap=True)
+        xd, gd, std = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8,
+                                    state=zero_state(B, m, n), k0=0, gap=True, return_state=True)
         assert np.array_equal(bits(x), bits(xd)), (B, iters)
+        assert torch.equal(g, gd), (B, iters)
+        xs, st = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8, workspace=ws,
+                               return_state=True)
+        assert np.array_equal(bits(xs), bits(xd)), (B, iters)
+        assert np.array_equal(bits(st), bits(std)), (B, iters)
 
 
 def test_support_of_one_pixel_and_of_nothing():
