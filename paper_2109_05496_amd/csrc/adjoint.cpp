@@ -28,17 +28,19 @@ int adj_tiles_x(int n, int h) { return (n + (64 - 2 * h) - 1) / (64 - 2 * h); }
 int adj_tiles_y(int m, int h) { return (m + (adj_tile_rows() - 2 * h) - 1) / (adj_tile_rows() - 2 * h); }
 
 struct BwdLayout {
-  size_t seg, adj, lam, total;
+  size_t seg, adj, lam, live, total;
 };
 
 BwdLayout layout(int batch, int m, int n, int ckpt) {
   BwdLayout L;
   const size_t st = align_up(state_bytes(batch, m, n));
   const int h = adj_halo(ckpt);
+  const size_t tiles = (size_t)adj_tiles_x(n, h) * adj_tiles_y(m, h);
   L.seg = (size_t)std::max(ckpt, 1) * st;
   L.adj = 2 * st;
-  L.lam = align_up((size_t)batch * adj_tiles_x(n, h) * adj_tiles_y(m, h) * sizeof(double));
-  L.total = L.seg + L.adj + L.lam;
+  L.lam = align_up((size_t)batch * tiles * sizeof(double));
+  L.live = align_up((2 * tiles + 1) * sizeof(int));  // flags, then the live-tile list
+  L.total = L.seg + L.adj + L.lam + L.live;
   return L;
 }
 
@@ -89,6 +91,7 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
   float* adjX = reinterpret_cast<float*>(wsb + L.seg);
   float* adjY = reinterpret_cast<float*>(wsb + L.seg + st_stride);
   double* lam_acc = reinterpret_cast<double*>(wsb + L.seg + L.adj);
+  int* live_mem = reinterpret_cast<int*>(wsb + L.seg + L.adj + L.lam);
 
   // x = P_C(b) for every image when K = 0; lambda = 0 images go through the
   // general path (step 0 keeps q = 0) with a zero lambda gradient.
@@ -142,6 +145,30 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
     }
     float* cur = adjX + st_off;
     float* nxt = adjY + st_off;
+    // With a support the adjoint state stays zero wherever the forward dual
+    // does (outside the support, no support pixel below or to the right): the
+    // reverse steps run only the tiles holding other pixels, after both
+    // adjoint buffers got their zeros there. The output step runs every tile.
+    const int* live = nullptr;
+    if (support) {
+      LiveScanArgs la;
+      la.mask = support;
+      la.m = m;
+      la.n = n;
+      la.halo = halo;
+      la.rows = adj_tile_rows();
+      la.tiles_x = tiles_x;
+      la.tiles_y = tiles_per_img / tiles_x;
+      la.flags = live_mem;
+      la.zero_st = 1;
+      la.st0 = cur;
+      la.st1 = nxt;
+      la.x = nullptr;
+      la.batch = cb;
+      hipError_t e = launch_live_tiles(la, live_mem + tiles_per_img, s);
+      if (e != hipSuccess) return hip_fail(e, "adjoint live-tile scan");
+      live = live_mem + tiles_per_img;
+    }
     auto slot = [&](int j) { return seg + (size_t)j * (st_stride / 4) + st_off; };
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
       const int ks = sgi * c, ke = std::min(ks + c, K);
@@ -180,6 +207,7 @@ ctv_status ctv_denoise_backward(const ctv_params* p, int32_t batch, int32_t m, i
         a.steps = steps;
         a.adj_in = cur;
         a.adj_out = (khi - steps + 1 == 1) ? nullptr : nxt;
+        a.live = live;
         hipError_t e = launch_adj_step(a, p->tv_kind, p->constraint, cb, s);
         if (e != hipSuccess) return hip_fail(e, "adjoint step");
         std::swap(cur, nxt);

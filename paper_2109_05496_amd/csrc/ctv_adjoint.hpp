@@ -28,6 +28,8 @@ struct AdjStepArgs {
   float lam[kPlainChunk];
   float c[kPlainChunk];     // 1/(8 lambda)
   float cc[kPlainChunk];    // 1/(8 lambda^2) (0 for lambda = 0)
+  const int* live;          // reverse steps only: [0] = L, [1 .. L] = the tiles (of one image) to run,
+                            // or nullptr for all (the grid stays one workgroup per tile of the chunk)
 };
 
 int adj_tile_rows();

@@ -405,10 +405,27 @@ __device__ __forceinline__ void adj_out_tile(const AdjJob& J, const int H, const
 
 constexpr int kNW = 8, kP = 4;
 
-__device__ __forceinline__ void adj_job_common(const AdjStepArgs& A, int& img, AdjJob& J) {
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  img = tile / A.tiles_per_img;
-  const int t = tile - img * A.tiles_per_img;
+// Returns false for a workgroup with no tile (live-tile list shorter than the grid).
+__device__ __forceinline__ bool adj_job_common(const AdjStepArgs& A, int& img, AdjJob& J) {
+  int t;
+  if (A.live) {
+    // Only the live tiles, each XCD one contiguous slice of the entries (as in
+    // the forward kernels); the tile keeps its own lambda-gradient slot.
+    const int L = A.live[0];
+    const int total = (gridDim.x / A.tiles_per_img) * L;
+    constexpr int kXcd = 8;
+    const int x = blockIdx.x % kXcd, i = blockIdx.x / kXcd;
+    const int q = total / kXcd, rem = total % kXcd;
+    if (i >= q + (x < rem ? 1 : 0)) return false;
+    const int e = x * q + (x < rem ? x : rem) + i;
+    img = e / L;
+    t = A.live[1 + (e - img * L)];
+  } else {
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    img = tile / A.tiles_per_img;
+    t = tile - img * A.tiles_per_img;
+  }
+  const int tile = img * A.tiles_per_img + t;
   const long long px = (long long)A.m * A.n;
   J.b = reinterpret_cast<const float2*>(A.b) + img * px;
   J.mask = A.mask;
@@ -424,6 +441,7 @@ __device__ __forceinline__ void adj_job_common(const AdjStepArgs& A, int& img, A
   J.cc = A.cc[img];
   J.R = A.R;
   J.steps = A.steps;
+  return true;
 }
 
 // Occupancy pinned at 4 waves per SIMD: left free, the type-1a and type-2i
@@ -434,7 +452,7 @@ __global__ __launch_bounds__(kNW * 64) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ double red[kNW];
   int img;
   AdjJob J;
-  adj_job_common(A, img, J);
+  if (!adj_job_common(A, img, J)) return;
   const long long px = (long long)A.m * A.n;
   // plane 1 (r) of each step's state
   auto rplane = [&](const float* r) { return r ? reinterpret_cast<const float4*>(r) + img * 2 * px + px : nullptr; };
@@ -459,7 +477,7 @@ __global__ __launch_bounds__(kNW * 64) void adj_output_kernel(AdjStepArgs A) {
   __shared__ double red[kNW];
   int img;
   AdjJob J;
-  adj_job_common(A, img, J);
+  if (!adj_job_common(A, img, J)) return;
   const long long px = (long long)A.m * A.n;
   J.r[0] = reinterpret_cast<const float4*>(A.r[0]) + img * 2 * px;  // plane 0 (q_K) of the final state
   J.adj_in = nullptr;
