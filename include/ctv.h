@@ -271,7 +271,9 @@ int32_t ctv_tune_cache_size(void);
  * support and params). Complex gradients use the real-pair convention of
  * Section II: grad = dL/dRe + i dL/dIm (what PyTorch returns for a real loss).
  * At the non-smooth points of the projections the Jacobian is the identity
- * when the norm is <= the radius (zero for a zero radius).
+ * when the norm is <= the radius (zero for a zero radius). With a support, the
+ * reverse steps skip the tiles where the adjoint state provably stays zero
+ * (the pixels where ctv_denoise's dual does), as ctv_denoise does.
  *   grad_x       [batch][m][n] complex64 incoming gradient.
  *   grad_b       [batch][m][n] complex64 output.
  *   grad_lambda  [batch] floats (device) output; 0 where lambda = 0 or K = 0.
