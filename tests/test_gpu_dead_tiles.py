@@ -75,6 +75,9 @@ def test_skipping_is_bitwise_invisible(kind):
             # gap variant also keeps the final state in one of them
             xg = ctv().denoise(bt, 0.07, gap=True, workspace=ws, **kw)[0]
             assert np.array_equal(bits(xg), bits(x)), (tile, fuse)
+            # x alone, from a fresh NaN-filled workspace
+            xr = ctv().denoise(bt, 0.07, workspace=nan_workspace(m, n, 1, kind, iters, fuse), **kw)
+            assert np.array_equal(bits(xr), bits(x)), (tile, fuse)
 
 
 def test_skipping_matches_oracle_and_reused_workspace():
@@ -133,6 +136,9 @@ def test_tilings_chunks_and_single_launch():
                                     state=zero_state(B, m, n), k0=0, gap=True, return_state=True)
         assert np.array_equal(bits(x), bits(xd)), (B, iters)
         assert torch.equal(g, gd), (B, iters)
+        xr = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8,
+                           workspace=nan_workspace(m, n, B, "1a", iters, 8))
+        assert np.array_equal(bits(xr), bits(xd)), (B, iters)
         xs, st = ctv().denoise(bt, lams, kind="1a", support=mk, iters=iters, fuse=8, workspace=ws,
                                return_state=True)
         assert np.array_equal(bits(xs), bits(xd)), (B, iters)
@@ -219,7 +225,8 @@ def test_random_supports_plain_and_batched():
         b = (rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))).astype(np.complex64)
         mk = blob_mask(m, n, rng)
         bt, mt = dev(b), dev(mk)
-        x = ctv().denoise(bt, 0.1, kind=kind, support=mt, iters=K, fuse=fuse, tile=tile)
+        x = ctv().denoise(bt, 0.1, kind=kind, support=mt, iters=K, fuse=fuse, tile=tile,
+                          workspace=nan_workspace(m, n, 1, kind, K, fuse))
         xd = ctv().denoise(bt, 0.1, kind=kind, support=mt, iters=K, fuse=fuse, tile=tile,
                            state=zero_state(1, m, n), k0=0)
         assert np.array_equal(bits(x), bits(xd)), (case, m, n, kind, K, fuse, tile)
