@@ -23,7 +23,8 @@ pr        angular-spectrum propagation (Eq. 23), the amplitude data term (Eq. 24
           and its gradient (Eq. 27), and FISTA (Algorithm 1) with the FGP prox.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
-``tests/test_oracle_*.py`` except the full phase-retrieval loop ``pr.fista``,
-whose end-to-end iterates are "parity unpinned" (the paper prints no values;
-only its stages and qualitative behaviour are pinned).
+``tests/test_oracle_*.py``. The phase-retrieval loop ``pr.fista`` is pinned by
+Algorithm 1's closed form on a problem without measurements (every iterate a
+known multiple of x_0) and by the qualitative behaviour on real data; the paper
+prints no iterates of its own.
 """

@@ -24,8 +24,13 @@ Readings where the paper is silent:
     with the momentum restarted (r_1 = q_0, t_1 = 1).
 
 Parity status: ``transfer``, ``A``, ``AH``, ``data_term`` and ``grad_F`` are
-pinned by closed forms and finite differences; ``fista``'s end-to-end iterates
-are parity unpinned (the paper prints no values).
+pinned by closed forms and finite differences. ``fista`` is pinned by Algorithm
+1's closed form on a problem without measurements (y = 0, so F = (D/2)||x||^2 and
+grad F = D x on a grid without evanescent frequencies; tau = 0, so the prox is
+P_C): every iterate is a real multiple of x_0 given by a scalar recurrence, with
+and without the modulus projection, with and without momentum, for one and
+several distances, and the backtracking line search accepts exactly the steps
+gamma <= 1 there. The paper prints no iterates of its own for a real problem.
 """
 import numpy as np
 

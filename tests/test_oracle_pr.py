@@ -2,6 +2,8 @@
 the angular-spectrum transfer function's closed-form properties, the data-term
 gradient against finite differences and its closed-form special cases, and the
 qualitative behaviour of Algorithm 1."""
+import math
+
 import numpy as np
 import pytest
 
@@ -162,3 +164,116 @@ def test_warm_started_prox_reaches_the_same_minimiser(rng):
     xl_c, _ = pr.fista(y, dists, wl, px, outer=3, inner=3000, tau=0.01, gamma=0.5)
     xl_w, _ = pr.fista(y, dists, wl, px, outer=3, inner=3000, tau=0.01, gamma=0.5, warm_start=True)
     np.testing.assert_allclose(xl_w, xl_c, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 in closed form. With no measurements (y = 0) the data term of
+# Eq. (24) is F(x) = (D/2)||x||^2 on a grid without evanescent frequencies
+# (each A_d is unitary), so grad F(x) = D x (Eq. 27 with sqrt(y) = 0). With
+# tau = 0 the prox of Eq. (15) is P_C alone (lambda = 0), the identity for
+# C = C^{m x n}. Every iterate is then a real multiple of x_0, and the
+# multiples obey a scalar recurrence that follows Algorithm 1 step by step:
+#   x_k = prox(z_k - gamma D z_k),  t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+#   z_{k+1} = x_k + ((t_k - 1) / t_{k+1}) (x_k - x_{k-1}),  z_1 = x_0,  t_1 = 1.
+# A momentum index shifted by one, the gradient taken at x_k instead of z_k,
+# or z reset to x_k each change the multiples from k = 2 or 3 on.
+# ---------------------------------------------------------------------------
+_WL, _PX = 532e-9, 4e-6
+
+
+def _scalar_fista(K, contraction, accelerate=True, clip=None):
+    """Multiples (c_z[1..K], c_x[0..K]) of x_0 for the reduced problem:
+    x_k = P(contraction * z_k), P = identity or the modulus clip of a
+    constant image of modulus `clip` (|.| <= 1 after scaling)."""
+    t = 1.0
+    cx = [1.0]
+    cz = [1.0]
+    for k in range(1, K + 1):
+        v = contraction * cz[-1]
+        if clip is not None:
+            v = v / max(1.0, abs(v) * clip)
+        cx.append(v)
+        t_next = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+        beta = (t - 1.0) / t_next if accelerate else 0.0
+        cz.append(cx[k] + beta * (cx[k] - cx[k - 1]))
+        t = t_next
+    return np.array(cz[:K]), np.array(cx)
+
+
+def _no_measurement_problem(rng, m=8, n=12, D=1):
+    dists = (1.0e-3, 2.5e-3, 1.5e-3)[:D]
+    y = np.zeros((D, m, n))
+    x0 = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    return y, dists, x0
+
+
+def test_momentum_sequence_first_values():
+    """t_2 = (1 + sqrt 5)/2 (the golden ratio), t_3 = (1 + sqrt(1 + 4 t_2^2))/2 =
+    (1 + sqrt(7 + 2 sqrt 5))/2, and t_k >= (k + 1)/2 (Beck and Teboulle's bound);
+    at gamma D = 1/2 the multiples are c_x = 1, 1/2, 1/4, (1/8)(1 - beta_2)...
+    with beta_2 = (t_2 - 1)/t_3."""
+    t2 = (1 + math.sqrt(5)) / 2
+    t3 = (1 + math.sqrt(7 + 2 * math.sqrt(5))) / 2
+    cz, cx = _scalar_fista(3, 0.5)
+    np.testing.assert_allclose(cx[:3], [1.0, 0.5, 0.25], rtol=0, atol=0)
+    np.testing.assert_allclose(cz[2], 0.25 - 0.25 * (t2 - 1) / t3, rtol=1e-15)
+    np.testing.assert_allclose(cx[3], 0.125 * (1 - (t2 - 1) / t3), rtol=1e-15)
+    t = 1.0
+    for k in range(1, 200):
+        assert t >= (k + 1) / 2 - 1e-12
+        t = (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+
+
+@pytest.mark.parametrize("D,gamma", [(1, 0.5), (2, 0.25), (3, 0.3)])
+def test_fista_iterates_follow_the_scalar_recurrence(rng, D, gamma):
+    """Every z_k (through F(z_k) = (D/2) c_z[k]^2 ||x_0||^2, the returned loss
+    trace) and the final x_K = c_x[K] x_0 match the recurrence, for one and for
+    several distances (the gradient is summed over d)."""
+    K = 12
+    y, dists, x0 = _no_measurement_problem(rng, D=D)
+    x, loss = pr.fista(y, dists, _WL, _PX, outer=K, inner=5, tau=0.0, gamma=gamma,
+                       constraint="none", x0=x0)
+    cz, cx = _scalar_fista(K, 1.0 - gamma * D)
+    nx0 = float(np.sum(np.abs(x0) ** 2))
+    np.testing.assert_allclose(loss, 0.5 * D * cz ** 2 * nx0, rtol=1e-11)
+    np.testing.assert_allclose(x, cx[K] * x0, rtol=0, atol=1e-12 * np.abs(x0).max())
+    # the momentum matters: the same problem without it is the geometric sequence
+    xi, li = pr.fista(y, dists, _WL, _PX, outer=K, inner=5, tau=0.0, gamma=gamma,
+                      constraint="none", x0=x0, accelerate=False)
+    np.testing.assert_allclose(xi, (1.0 - gamma * D) ** K * x0, rtol=0, atol=1e-13 * np.abs(x0).max())
+    assert abs(cx[K] - (1.0 - gamma * D) ** K) > 1e-3 * abs(cx[K])
+
+
+def test_fista_recurrence_with_the_modulus_projection():
+    """With C = {|x| <= 1} the prox is the pixelwise projection of Eq. 26. For a
+    constant image x_0 = 4 e^{i 0.7} every iterate stays constant, the first prox
+    clips (|x_0|/2 = 2 > 1) and later ones do not; the recurrence with the clip
+    reproduces all of them (the prox acts after the gradient step, not before)."""
+    K = 8
+    m, n = 6, 5
+    x0 = np.full((m, n), 4.0 * np.exp(0.7j))
+    y = np.zeros((1, m, n))
+    x, loss = pr.fista(y, (1.0e-3,), _WL, _PX, outer=K, inner=3, tau=0.0, gamma=0.5,
+                       constraint="modulus", x0=x0)
+    cz, cx = _scalar_fista(K, 0.5, clip=4.0)
+    assert cx[1] == 0.25  # 4 * 0.25 = 1: the first prox lands on the circle
+    np.testing.assert_allclose(loss, 0.5 * cz ** 2 * 16.0 * m * n, rtol=1e-11)
+    np.testing.assert_allclose(x, cx[K] * x0, rtol=0, atol=1e-12)
+
+
+def test_line_search_steps_in_closed_form(rng):
+    """Backtracking on F = (1/2)||x||^2 (one distance, identity prox): the
+    quadratic model holds at x = (1 - gamma) z exactly when gamma <= 1
+    ((1 - gamma)^2 <= 1 - gamma). Starting from gamma = 3 with shrink 1/2, the
+    steps 3 and 1.5 are rejected and 0.75 is accepted on the third trial; later
+    iterations keep 0.75 and accept at once, so the iterates follow the
+    recurrence with contraction 1/4."""
+    K = 6
+    y, dists, x0 = _no_measurement_problem(rng, D=1)
+    x, loss, info = pr.fista(y, dists, _WL, _PX, outer=K, inner=4, tau=0.0, gamma=3.0,
+                             constraint="none", x0=x0, line_search=True, shrink=0.5, return_info=True)
+    np.testing.assert_array_equal(info["trials"], [3] + [1] * (K - 1))
+    np.testing.assert_array_equal(info["gamma"], [0.75] * K)
+    cz, cx = _scalar_fista(K, 0.25)
+    np.testing.assert_allclose(loss, 0.5 * cz ** 2 * float(np.sum(np.abs(x0) ** 2)), rtol=1e-11)
+    np.testing.assert_allclose(x, cx[K] * x0, rtol=0, atol=1e-12 * np.abs(x0).max())
