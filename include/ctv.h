@@ -108,6 +108,13 @@ typedef struct {
 int32_t ctv_version(void);
 const char* ctv_last_error(void);
 
+/* Test hook for the failure path of CTV_S_FLOW (callers: the library's own
+ * tests). on != 0 makes every later CTV_S_FLOW launch in this process start
+ * with its wait-failure flag raised, so each neighbour wait gives up at once,
+ * as after a real timeout; the kernels still exit normally and x (and
+ * state_out) come back NaN. on = 0 restores normal runs. Always CTV_OK. */
+ctv_status ctv_debug_flow_fail_waits(int32_t on);
+
 /* Workspace (and checkpoint storage) needed by ctv_denoise /
  * ctv_denoise_backward for `batch` images of m x n.
  *   ws_bytes    : scratch for ctv_denoise; ctv_denoise_backward needs
@@ -152,9 +159,15 @@ ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, 
  * those of computing them, for finite b). The call then launches two small
  * kernels per tiling that list the other tiles.
  * Errors: CTV_ERR_INVALID_ARG (null/negative/out-of-range arguments, unknown
- * kind/constraint, alpha outside [0,1], lambda < 0 or non-finite, m or n < 1,
- * struct_size mismatch), CTV_ERR_WORKSPACE (ws_bytes too small),
- * CTV_ERR_HIP (a launch failed). */
+ * kind/constraint, alpha outside [0,1], lambda < 0, non-finite or inside
+ * (0, 1e-12) - there the float32 dual step 1/(8 lambda) and the backward's
+ * 1/(8 lambda^2) overflow; pass 0 instead: since P_C is nonexpansive and
+ * |L^T q| <= 4 per channel on the dual set, P_C(b) is within 6 lambda of the
+ * K-step result at every pixel - m or n < 1, struct_size mismatch),
+ * CTV_ERR_WORKSPACE (ws_bytes too small), CTV_ERR_HIP (a launch failed).
+ * CTV_S_FLOW's neighbour waits are bounded (about a second each); if one gives
+ * up, the affected pixels of x and of state_out are NaN (never silently wrong
+ * values). */
 ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n, const float* b,
                        const float* lambda_host, const uint8_t* support, float* x, double* gap,
                        const float* state_in, int32_t k0, float* state_out, int32_t ckpt_every,
@@ -309,7 +322,8 @@ typedef struct {
   const double* distances_host;  /* [D] propagation distances (m) */
   double wavelength;             /* illumination wavelength (m), > 0 */
   double pixel;                  /* sampling pitch (m), > 0 */
-  float tau;                     /* TV weight >= 0 */
+  float tau;                     /* TV weight: 0, or tau * (initial gamma) >= 1e-12 (a smaller prox
+                                    weight, reachable only by backtracking, is taken as 0) */
   float gamma;                   /* step size > 0 (0 = 1/D) */
   int32_t outer_iters;           /* K_out >= 0 */
   ctv_params inner;              /* prox: kind, alpha, constraint, iters = K_in, fuse */

@@ -59,6 +59,7 @@ class Tuning(ctypes.Structure):
 _SIGS = {
     "ctv_version": (c_i32, []),
     "ctv_last_error": (ctypes.c_char_p, []),
+    "ctv_debug_flow_fail_waits": (c_i32, [c_i32]),
     "ctv_tiling": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, ctypes.POINTER(c_i32),
                            ctypes.POINTER(c_i32), ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "ctv_workspace_size": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_i32, c_psz, c_psz]),

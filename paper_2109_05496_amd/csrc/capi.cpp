@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -17,6 +18,9 @@
 namespace ctv {
 
 thread_local std::string g_last_error;
+
+// Test hook of the dataflow schedule (ctv_debug_flow_fail_waits).
+static std::atomic<int> g_flow_fail_waits{0};
 
 ctv_status fail(ctv_status st, const std::string& msg) {
   g_last_error = msg;
@@ -43,6 +47,11 @@ ctv_status validate_params(const ctv_params* p) {
 
 ctv_status validate_lambda(float lam) {
   if (!(lam >= 0.0f) || !std::isfinite(lam)) return fail(CTV_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  // The dual step 1/(8 lambda), the squared dual norms it feeds and the
+  // backward's 1/(8 lambda^2) must stay finite in float32: below ~2e-20 the
+  // latter overflows, and for subnormal lambda the step itself is infinite.
+  if (lam > 0.0f && lam < kMinLambda)
+    return fail(CTV_ERR_INVALID_ARG, "lambda must be 0 or >= 1e-12 (smaller values overflow the float32 dual step)");
   return CTV_OK;
 }
 
@@ -189,6 +198,11 @@ extern "C" {
 int32_t ctv_version(void) { return 100; }
 
 const char* ctv_last_error(void) { return g_last_error.c_str(); }
+
+ctv_status ctv_debug_flow_fail_waits(int32_t on) {
+  g_flow_fail_waits.store(on ? 1 : 0);
+  return CTV_OK;
+}
 
 ctv_status ctv_workspace_size(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
                               int32_t ckpt_every, size_t* ws_bytes, size_t* saved_bytes) {
@@ -344,6 +358,7 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
         const long long ints = flow_ints(cb, m, n, fa.halo);
         fa.counter = flow_mem;
         fa.err = flow_mem + 1;
+        fa.preset_err = g_flow_fail_waits.load();
         fa.done = flow_mem + 64;
         hipError_t e = launch_zero_f4(reinterpret_cast<float*>(flow_mem), (ints + 3) / 4, s);
         if (e == hipSuccess) e = launch_fgp_flow(fa, p->tv_kind, p->constraint, s);

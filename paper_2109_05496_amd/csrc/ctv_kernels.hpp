@@ -49,7 +49,8 @@ struct FgpFlowArgs {
   float* x;               // complex64 output
   int* counter;           // ticket counter, zero at launch
   int* done;              // [chunk][tiles]: steps completed, zero at launch
-  int* err;               // set to 1 if a dependency wait gave up (results then invalid)
+  int* err;               // set to 1 if a dependency wait gave up; the epilogue then writes NaN
+  int preset_err;         // test hook: raise *err at launch, so every wait gives up at once
   int m, n, tiles_x, tiles_y, batch;
   int halo;               // = T for every step
   int T, T_last, steps;   // fused iterations per step (last compute step: T_last), compute steps

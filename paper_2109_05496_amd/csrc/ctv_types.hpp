@@ -8,6 +8,10 @@ enum Constr { C_NONE = 0, C_MOD = 1 };
 
 constexpr int kMaxFuse = 16;
 
+// Smallest positive lambda accepted: 1/(8 lambda^2) (the backward's step
+// derivative) and the squared dual norms stay far from float32 overflow.
+constexpr float kMinLambda = 1e-12f;
+
 // Radii of the dual balls: type-I uses 1; type-II uses alpha for the real
 // plane's dual (r) and 1 - alpha for the imaginary plane's dual (s).
 struct Radii {

@@ -399,7 +399,29 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 // loads and crosses a barrier before loading. Every wait is bounded: after kFlowSpin
 // polls (about a second) it records the failure in *err and proceeds, and
 // every other wait then stops at its next check, so the grid always drains.
+// A task that proceeds without its inputs may compute wrong values, and so may
+// every task that depends on it; all of them come after the failure was
+// recorded, so an epilogue task that finds *err set writes NaN into its output
+// pixels of x and of the returned state instead of Eq. (18). Results are
+// therefore either exact or NaN, never silently wrong.
 constexpr int kFlowSpin = 1 << 20;
+
+// NaN into the output pixels of one tile of one image (x and, if given, both
+// planes of the returned state): the dataflow schedule's failure report.
+__device__ void flow_fail_tile(float2* x, float4* st, int m, int n, int tx, int ty, int OW, int OH) {
+  const float nan = __builtin_nanf("");
+  const int k = tx * OW + (int)(threadIdx.x & 63);
+  if ((int)(threadIdx.x & 63) >= OW || k >= n) return;
+  const long long plane = (long long)m * n;
+  for (int j = ty * OH + (int)(threadIdx.x >> 6); j < min(m, (ty + 1) * OH); j += (int)(blockDim.x >> 6)) {
+    const long long p = (long long)j * n + k;
+    if (x) x[p] = make_float2(nan, nan);
+    if (st) {
+      st[p] = make_float4(nan, nan, nan, nan);
+      st[plane + p] = make_float4(nan, nan, nan, nan);
+    }
+  }
+}
 
 template <int KIND, int CONSTR, bool MASK>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void fgp_flow_kernel(FgpFlowArgs A) {
@@ -408,11 +430,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void f
   __shared__ float2 sTop[NW * kRW];
   __shared__ float sBeta[kMaxFuse];
   __shared__ int sTicket;
+  __shared__ int sErr;
   const int per_img = A.tiles_x * A.tiles_y;
   const int per_step = per_img * A.batch;
   const int total = per_step * (A.steps + 1);
   const long long px = (long long)A.m * A.n;
   const int H = A.halo;
+  if (A.preset_err && threadIdx.x == 0) __hip_atomic_store(A.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
     __syncthreads();  // the previous task is done with LDS
     if (threadIdx.x == 0) sTicket = atomicAdd(A.counter, 1);
@@ -448,8 +472,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void f
     const bool epi = (st == A.steps);
     const int T = epi ? 0 : (st == A.steps - 1 ? A.T_last : A.T);
     if (threadIdx.x < kMaxFuse) sBeta[threadIdx.x] = ((int)threadIdx.x < T) ? A.beta[st * A.T + threadIdx.x] : 0.0f;
+    if (threadIdx.x == 0) sErr = epi ? __hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     __syncthreads();
     float* in_buf = (st % 2 == 0) ? A.buf0 : A.buf1;
+    if (sErr) {
+      // A wait gave up somewhere and this tile's output may depend on it. The
+      // last chunk of a call reports it in x and the returned state; an
+      // earlier chunk (no x) in the state the next chunk starts from, where
+      // the NaN spreads to x.
+      float4* fst = A.x ? reinterpret_cast<float4*>(A.st_out) : reinterpret_cast<float4*>(in_buf);
+      flow_fail_tile(A.x ? reinterpret_cast<float2*>(A.x) + img * px : nullptr, fst ? fst + img * 2 * px : nullptr,
+                     A.m, A.n, tx, ty, kRW - 2 * H, NW * P - 2 * H);
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_store(done_img + t, st + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
     float* out_buf = (st % 2 == 0) ? A.buf1 : A.buf0;
     const float* src = (st == 0) ? A.st_in : in_buf;
     float* dst = epi ? A.st_out : out_buf;
@@ -458,7 +495,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void f
     J.mask = A.mask;
     J.st_in = src ? reinterpret_cast<const float4*>(src) + img * 2 * px : nullptr;
     J.st_out = dst ? reinterpret_cast<float4*>(dst) + img * 2 * px : nullptr;
-    J.x = epi ? reinterpret_cast<float2*>(A.x) + img * px : nullptr;
+    J.x = (epi && A.x) ? reinterpret_cast<float2*>(A.x) + img * px : nullptr;  // no x before the last chunk
     J.m = A.m;
     J.n = A.n;
     J.ty = ty;

@@ -72,6 +72,9 @@ ctv_status validate_pr(const pr_params* p, int m, int n, bool need_inner) {
   if (need_inner) {
     if (!(p->tau >= 0.0f) || !std::isfinite(p->tau)) return fail(CTV_ERR_INVALID_ARG, "tau must be >= 0");
     if (!(p->gamma >= 0.0f) || !std::isfinite(p->gamma)) return fail(CTV_ERR_INVALID_ARG, "gamma must be >= 0");
+    const double g0 = p->gamma > 0.0f ? (double)p->gamma : 1.0 / p->num_meas;
+    if (p->tau > 0.0f && (double)p->tau * g0 < (double)kMinLambda)
+      return fail(CTV_ERR_INVALID_ARG, "tau * gamma must be 0 or >= 1e-12 (the prox's lambda)");
     if (p->outer_iters < 0) return fail(CTV_ERR_INVALID_ARG, "outer_iters must be >= 0");
     ctv_status st = validate_params(&p->inner);
     if (st) return st;
@@ -397,6 +400,9 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   // x_k = prox_{gamma R}(v): Algorithm 2 with lambda = tau gamma from q_0 = 0 or
   // the warm dual; with the warm start the last launch also stores its state.
   auto prox = [&](float lam) -> ctv_status {
+    // A weight the denoiser rejects (0 < tau gamma < 1e-12, reachable only by
+    // backtracking far) is taken as 0: P_C alone, within 6 tau gamma per pixel.
+    if (lam < kMinLambda) lam = 0.0f;
     int kk = 0;
     const float* src = (warm && have_warm) ? wcur : nullptr;
     do {

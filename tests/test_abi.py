@@ -51,7 +51,8 @@ def denoise_status(p, batch=1, m=8, n=8, lam=0.1, b=DUMMY, x=ctypes.c_void_p(0x2
 @pytest.mark.parametrize("bad", [
     dict(p=dict(kind="1i"), batch=0), dict(p=dict(kind="1i"), m=0), dict(p=dict(kind="1i"), n=-3),
     dict(p=dict(kind="1i"), lam=-0.1), dict(p=dict(kind="1i"), lam=float("nan")),
-    dict(p=dict(kind="1i"), lam=float("inf")), dict(p=dict(kind="1i", iters=-1)),
+    dict(p=dict(kind="1i"), lam=float("inf")), dict(p=dict(kind="1i"), lam=1e-13),
+    dict(p=dict(kind="1i"), lam=1e-40), dict(p=dict(kind="1i", iters=-1)),
     dict(p=dict(kind="2i", alpha=1.5)), dict(p=dict(kind="2i", alpha=-0.1)),
     dict(p=dict(kind="1i", fuse=17)), dict(p=dict(kind="1i"), b=None), dict(p=dict(kind="1i"), x=None),
     dict(p=dict(kind="1i"), ws=None), dict(p=dict(kind="1i"), k0=3),
@@ -114,3 +115,20 @@ def test_phase_retrieval_line_search_arguments_rejected():
         st = _lib.lib().pr_prox_grad(ctypes.byref(p), 8, 8, DUMMY, DUMMY, None, None, DUMMY, 1 << 40, None)
         assert st == INVALID, kw
         assert b"ls_" in _lib.lib().ctv_last_error()
+
+
+def test_smallest_lambda_accepted():
+    """lambda = 0 and lambda >= 1e-12 pass validation (the dummy pointers are
+    never reached because the workspace check fails first); 0 < lambda < 1e-12,
+    where 1/(8 lambda^2) overflows float32, is rejected."""
+    p = P(iters=10)
+    for lam in (0.0, 1e-12, 2e-12):
+        assert denoise_status(p, lam=lam, ws_bytes=1) == WORKSPACE, lam
+    for lam in (9e-13, 1e-20, 1e-45):
+        assert denoise_status(p, lam=lam, ws_bytes=1) == INVALID, lam
+        assert b"1e-12" in _lib.lib().ctv_last_error()
+
+
+def test_flow_failure_hook_is_exported_and_host_only():
+    assert _lib.lib().ctv_debug_flow_fail_waits(1) == 0
+    assert _lib.lib().ctv_debug_flow_fail_waits(0) == 0
