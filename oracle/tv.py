@@ -317,6 +317,14 @@ def gap_groups(q, b, lam, kind="1i", alpha=0.5, constraint="modulus", mask=None)
     group's term is >= 0 by Cauchy-Schwarz when q lies in S.
     Returns (total, per_group_min)."""
     x = primal_from_dual(q, b, lam, constraint, mask)
+    return gap_at(x, q, lam, kind, alpha)
+
+
+def gap_at(x, q, lam, kind="1i", alpha=0.5):
+    """lam * sum_groups (||(L x)_g||_* - <q_g, (L x)_g>) for a given primal x
+    and dual q (the group sum of gap_groups without forming x(q)).
+    Returns (total, per_group_min)."""
+    x = np.asarray(x, dtype=np.complex128)
     u1, u2, v1, v2 = L_pair(x.real, x.imag)
     r1, r2, s1, s2 = q
     terms = []

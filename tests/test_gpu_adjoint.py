@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import synth
+from _parity import elem
 from oracle import adjoint as oadj
 from oracle import tv
 
@@ -59,6 +60,8 @@ def test_backward_matches_oracle_reverse(kind, constraint, shape, K):
     lam, alpha = 0.07, 0.35
     _, gb, gl = gpu_vjp(b, lam, K, xbar, kind, alpha, constraint)
     _, gbo, glo = oadj.fgp_vjp(b.astype(np.complex128), lam, K, xbar.astype(np.complex128), kind, alpha, constraint)
+    print("adjoint", kind, constraint, shape, K, "grad_b rel-L2", rel(gb[0], gbo), "elementwise", elem(gb[0], gbo),
+          "grad_lambda rel", abs(gl[0] - glo) / max(1.0, abs(glo)))
     assert rel(gb[0], gbo) <= TOL, (kind, constraint, shape, K, rel(gb[0], gbo))
     assert abs(gl[0] - glo) <= TOL * max(1.0, abs(glo)), (gl[0], glo)
 
@@ -71,6 +74,8 @@ def test_backward_with_mask(kind):
     _, gb, gl = gpu_vjp(b, 0.09, 25, xbar, kind, mask=mask)
     _, gbo, glo = oadj.fgp_vjp(b.astype(np.complex128), 0.09, 25, xbar.astype(np.complex128), kind, 0.5,
                                "modulus", mask)
+    print("adjoint masked", kind, "grad_b rel-L2", rel(gb[0], gbo), "elementwise", elem(gb[0], gbo),
+          "grad_lambda rel", abs(gl[0] - glo) / max(1.0, abs(glo)))
     assert rel(gb[0], gbo) <= TOL
     assert np.all(gb[0][mask == 0] == 0)
     assert abs(gl[0] - glo) <= TOL * max(1.0, abs(glo))
@@ -104,6 +109,7 @@ def test_autograd_function_matches_backward():
     loss.backward()
     xbar = (2 * (x.detach() - truth)).cpu().numpy()
     _, gbo, glo = oadj.fgp_vjp(b.astype(np.complex128), 0.06, 30, xbar.astype(np.complex128), "1i")
+    print("autograd grad_b rel-L2", rel(bt.grad.cpu().numpy(), gbo), "grad_lambda", lam.grad.item(), glo)
     assert rel(bt.grad.cpu().numpy(), gbo) <= TOL
     assert abs(lam.grad.item() - glo) <= TOL * max(1.0, abs(glo))
 
@@ -134,10 +140,10 @@ def test_config4_full_batch_against_finite_differences():
 
     fd_b = (f(b64 + h * d, c["lam"]) - f(b64 - h * d, c["lam"])) / (2 * h)
     an_b = float(np.sum(gb.real * d.real + gb.imag * d.imag))
-    print("config4 directional derivative: FD", fd_b, "GPU adjoint", an_b)
+    print("config4 directional derivative: FD", fd_b, "GPU adjoint", an_b, "rel", abs(an_b - fd_b) / abs(fd_b))
     assert abs(an_b - fd_b) <= TOL * abs(fd_b)
     fd_l = (f(b64, c["lam"] + h) - f(b64, c["lam"] - h)) / (2 * h)
-    print("config4 d/dlambda: FD", fd_l, "GPU adjoint", gl)
+    print("config4 d/dlambda: FD", fd_l, "GPU adjoint", gl, "rel", abs(gl - fd_l) / abs(fd_l))
     assert abs(gl - fd_l) <= TOL * abs(fd_l)
 
 

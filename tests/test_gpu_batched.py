@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import synth
+from _parity import ELEM_TOL, elem
 from oracle import tv
 
 torch = pytest.importorskip("torch")
@@ -63,6 +64,7 @@ def test_batched_equals_plain_bitwise_and_oracle():
         assert np.array_equal(x2.view(np.uint32), ref.view(np.uint32)), i
         xo = tv.fgp(b.astype(np.complex128), d["lam"], d["iters"], d["kind"], d["alpha"], "modulus", mask)
         assert rel(x1, xo) <= 1e-5, (i, rel(x1, xo))
+        assert elem(x1, xo) <= ELEM_TOL, (i, elem(x1, xo))
     plan.close()
 
 
@@ -95,6 +97,7 @@ def test_config3_full_batch_matches_plain_calls():
         d = imgs3[i]
         xo = tv.fgp(d["b"].astype(np.complex128), d["lam"], d["iters"], d["kind"])
         assert rel(out[i].cpu().numpy(), xo) <= 1e-5, i
+        assert elem(out[i].cpu().numpy(), xo) <= ELEM_TOL, i
     plan.close()
 
 
@@ -114,4 +117,5 @@ def test_batched_gradient_projection_method():
         xo = tv.fgp(b.astype(np.complex128), d["lam"], d["iters"], d["kind"], d["alpha"], "modulus", mask,
                     method="gp")
         assert rel(x, xo) <= 1e-5, (i, rel(x, xo))
+        assert elem(x, xo) <= ELEM_TOL, (i, elem(x, xo))
     plan.close()
