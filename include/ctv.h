@@ -173,6 +173,28 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
                        const float* state_in, int32_t k0, float* state_out, int32_t ckpt_every,
                        float* saved, void* ws, size_t ws_bytes, ctv_stream_t stream);
 
+/* ctv_denoise_noalloc - ctv_denoise for callers that cannot allocate device
+ * memory (code under HIP-graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same cold-start solve (no resume state, no
+ * checkpoints) with the workspace taken from a fixed device array that the
+ * library holds on every GPU it runs on until the process ends, instead of a
+ * caller buffer. The call allocates nothing; results are bitwise those of
+ * ctv_denoise. The current device must be the one `stream` belongs to.
+ *   Arguments as in ctv_denoise (gap may be NULL).
+ *   Limit: ctv_workspace_size(p, batch, m, n, 0) must not exceed
+ *   CTV_NOALLOC_SCRATCH_BYTES (72 MiB: one 1024 x 1024 image, or four
+ *   512 x 512 images); larger problems fail with CTV_ERR_WORKSPACE before any
+ *   device work.
+ *   Calls on one GPU share that GPU's array: two calls that may overlap in time
+ *   (different streams, or different host threads without ordering) race and
+ *   give wrong results; calls ordered on one stream are safe. Nothing needs to
+ *   start at zero: the kernels write every workspace word they read.
+ * Errors: those of ctv_denoise, plus CTV_ERR_WORKSPACE above the limit. */
+#define CTV_NOALLOC_SCRATCH_BYTES (72u * 1024u * 1024u)
+ctv_status ctv_denoise_noalloc(const ctv_params* p, int32_t batch, int32_t m, int32_t n, const float* b,
+                               const float* lambda_host, const uint8_t* support, float* x, double* gap,
+                               ctv_stream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batched ragged denoising: many images of different sizes, each with its own
  * lambda, TV kind, alpha and K, in one HIP-graph launch. Per image the result

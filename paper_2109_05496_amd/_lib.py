@@ -65,6 +65,8 @@ _SIGS = {
     "ctv_workspace_size": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_i32, c_psz, c_psz]),
     "ctv_denoise": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_f), c_vp,
                             c_vp, c_vp, c_vp, c_i32, c_vp, c_i32, c_vp, c_vp, c_sz, c_vp]),
+    "ctv_denoise_noalloc": (c_i32, [ctypes.POINTER(Params), c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_f), c_vp,
+                                    c_vp, c_vp, c_vp]),
     "ctv_batched_plan_create": (c_i32, [ctypes.POINTER(ImageDesc), c_i32, ctypes.POINTER(Params),
                                         ctypes.POINTER(c_vp)]),
     "ctv_batched_workspace_size": (c_i32, [c_vp, c_psz]),

@@ -132,3 +132,14 @@ def test_smallest_lambda_accepted():
 def test_flow_failure_hook_is_exported_and_host_only():
     assert _lib.lib().ctv_debug_flow_fail_waits(1) == 0
     assert _lib.lib().ctv_debug_flow_fail_waits(0) == 0
+
+
+def test_noalloc_refuses_problems_above_its_scratch_before_device_work():
+    p = P(iters=10)
+    lams = (ctypes.c_float * 1)(0.1)
+    st = _lib.lib().ctv_denoise_noalloc(ctypes.byref(p), 1, 2048, 2048, DUMMY, lams, None, ctypes.c_void_p(0x2000),
+                                        None, None)
+    assert st == WORKSPACE
+    assert b"72" in _lib.lib().ctv_last_error() or b"workspace" in _lib.lib().ctv_last_error()
+    assert _lib.lib().ctv_denoise_noalloc(ctypes.byref(p), 1, 8, 8, DUMMY, (ctypes.c_float * 1)(-1.0), None,
+                                          ctypes.c_void_p(0x2000), None, None) == INVALID
