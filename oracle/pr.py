@@ -23,6 +23,12 @@ Readings where the paper is silent:
     ``warm_start=True`` it starts from the previous prox's last dual iterate,
     with the momentum restarted (r_1 = q_0, t_1 = 1).
 
+The iterative projection baseline ``ip`` (Section VI-A) alternates the
+measured-modulus projection of each distance, in turn, with P_C; with several
+distances the paper is silent, and the sequential order is the reading taken
+(averaging the distances' projections instead is exactly one step of the
+proximal gradient iteration of Eq. 14 with tau = 0 and gamma = 1 / D).
+
 Parity status: ``transfer``, ``A``, ``AH``, ``data_term`` and ``grad_F`` are
 pinned by closed forms and finite differences. ``fista`` is pinned by Algorithm
 1's closed form on a problem without measurements (y = 0, so F = (D/2)||x||^2 and
@@ -31,6 +37,10 @@ P_C): every iterate is a real multiple of x_0 given by a scalar recurrence, with
 and without the modulus projection, with and without momentum, for one and
 several distances, and the backtracking line search accepts exactly the steps
 gamma <= 1 there. The paper prints no iterates of its own for a real problem.
+``ip`` is pinned by the noise-free fixed point at the truth, idempotence of
+each projection, the error-reduction inequality (with one distance F(x_k)
+never increases) and, with one distance, its identity with one proximal
+gradient step of step 1 whose prox is P_C alone.
 """
 import numpy as np
 
@@ -129,6 +139,38 @@ def fista(y, distances, wavelength, pixel, outer, inner, tau, gamma,
     if return_info:
         return x_prev, np.array(loss), {"gamma": np.array(steps), "trials": np.array(trials)}
     return x_prev, np.array(loss)
+
+
+def project_modulus(x, sqrt_y_d, H):
+    """Nearest point of {x : |A_d x| = sqrt(y_d)} (A_d unitary on the grid):
+    keep the phase of A_d x, impose the measured modulus, propagate back
+    (unit phasor where A_d x = 0)."""
+    ph, _ = _phasor(A(x, H))
+    return AH(sqrt_y_d * ph, H)
+
+
+def ip(y, distances, wavelength, pixel, iters, x0=None, constraint="modulus"):
+    """The iterative projection (IP) comparison method of Section VI-A: the
+    estimate is projected in turn onto the measured-modulus set of each
+    distance, each projection followed by the projection P_C onto the
+    nonnegative-absorption set of Eq. 25 (C = C^{m x n} for constraint="none").
+    With one distance this is the classic alternation between the two sets.
+    Starts from the back-propagated field unless x0 is given. Returns (x_K,
+    loss) with loss[k] = F(x_k), the data term of Eq. (24) summed over d, at the
+    start of iteration k + 1."""
+    y = np.asarray(y, dtype=np.float64)
+    D, m, n = y.shape
+    Hs = [transfer(m, n, d, wavelength, pixel) for d in distances]
+    sqrt_y = [np.sqrt(np.maximum(yy, 0.0)) for yy in y]
+    x = backprop(sqrt_y, Hs) if x0 is None else np.asarray(x0, dtype=np.complex128)
+    loss = []
+    for _ in range(iters):
+        loss.append(data_term(x, sqrt_y, Hs))
+        for s, H in zip(sqrt_y, Hs):
+            u = project_modulus(x, s, H)
+            pu, pv = _tv.P_C(u.real, u.imag, constraint)
+            x = pu + 1j * pv
+    return x, np.array(loss)
 
 
 def phase_rmse(x, truth):

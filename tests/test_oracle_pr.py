@@ -277,3 +277,90 @@ def test_line_search_steps_in_closed_form(rng):
     cz, cx = _scalar_fista(K, 0.25)
     np.testing.assert_allclose(loss, 0.5 * cz ** 2 * float(np.sum(np.abs(x0) ** 2)), rtol=1e-11)
     np.testing.assert_allclose(x, cx[K] * x0, rtol=0, atol=1e-12 * np.abs(x0).max())
+
+
+# ---------------------------------------------------------------------------
+# Iterative projection (IP) baseline, Section VI-A.
+# ---------------------------------------------------------------------------
+def _ip_problem(m=32, D=2, seed=3, noise=False):
+    truth = synth.config5_object(seed=seed, size=m, n_shapes=6, sigma_px=1.5)   # |truth| <= 1
+    dists = (1.0e-3, 2.0e-3, 1.5e-3)[:D]
+    Hs = [pr.transfer(m, m, d, _WL, _PX) for d in dists]
+    inten = [np.abs(pr.A(truth, H)) ** 2 for H in Hs]
+    if noise:
+        rng = np.random.default_rng(seed)
+        inten = [synth.poisson_measure(I, 1000.0, rng).astype(np.float64) for I in inten]
+    return truth, dists, Hs, np.stack(inten)
+
+
+def test_ip_noise_free_truth_is_a_fixed_point():
+    """With noise-free data and |x_true| <= 1, the truth lies in every
+    measured-modulus set and in C, so every projection leaves it in place."""
+    truth, dists, Hs, y = _ip_problem(D=3)
+    x, loss = pr.ip(y, dists, _WL, _PX, 3, x0=truth)
+    np.testing.assert_allclose(x, truth, rtol=0, atol=1e-12)
+    assert np.all(loss < 1e-20)
+
+
+def test_ip_projections_are_idempotent_and_land_in_their_sets(rng):
+    truth, dists, Hs, y = _ip_problem(D=1, noise=True)
+    sy = np.sqrt(y[0])
+    x = truth * np.exp(0.4j) + 0.2 * (rng.standard_normal(truth.shape) + 1j * rng.standard_normal(truth.shape))
+    u = pr.project_modulus(x, sy, Hs[0])
+    np.testing.assert_allclose(np.abs(pr.A(u, Hs[0])), sy, atol=1e-12)           # in the modulus set
+    np.testing.assert_allclose(pr.project_modulus(u, sy, Hs[0]), u, atol=1e-12)   # idempotent
+    # the nearest point: no other point of the set among random phase changes is closer
+    d0 = np.linalg.norm(u - x)
+    for _ in range(5):
+        v = pr.AH(sy * np.exp(1j * rng.uniform(-np.pi, np.pi, sy.shape)), Hs[0])
+        assert np.linalg.norm(v - x) >= d0 - 1e-12
+
+
+def test_ip_error_never_increases_with_one_distance():
+    """Alternating projections between the modulus set M and the convex set C:
+    dist(x_{k+1}, M) <= ||x_{k+1} - P_M x_k|| <= ||x_k - P_M x_k|| = dist(x_k, M),
+    and F(x) = dist(x, M)^2 / 2 for a unitary A."""
+    truth, dists, Hs, y = _ip_problem(D=1, noise=True)
+    # (the back-propagated start already has the measured modulus with one
+    # distance, so start elsewhere: a rotated, scaled, noisy copy of the truth)
+    rng = np.random.default_rng(4)
+    x0 = 1.3 * truth * np.exp(0.7j) + 0.3 * (rng.standard_normal(truth.shape) + 1j * rng.standard_normal(truth.shape))
+    _, loss = pr.ip(y, dists, _WL, _PX, 25, x0=x0)
+    assert np.all(np.diff(loss) <= 1e-12 * loss[:-1])
+    assert loss[-1] < 0.5 * loss[0]
+
+
+def test_ip_one_distance_equals_a_prox_gradient_step_with_projection_prox():
+    """With one distance, x - grad F(x) is the magnitude replacement (Eq. 27),
+    so one IP iteration is the proximal gradient step of Eq. (14) with gamma = 1
+    and tau = 0 (the prox is P_C alone)."""
+    truth, dists, Hs, y = _ip_problem(D=1, noise=True)
+    rng = np.random.default_rng(5)
+    x0 = 1.3 * truth * np.exp(0.7j) + 0.3 * (rng.standard_normal(truth.shape) + 1j * rng.standard_normal(truth.shape))
+    for constraint in ("modulus", "none"):
+        xi, li = pr.ip(y, dists, _WL, _PX, 3, x0=x0, constraint=constraint)
+        xf, lf = pr.fista(y, dists, _WL, _PX, outer=3, inner=4, tau=0.0, gamma=1.0, constraint=constraint,
+                          x0=x0, accelerate=False)
+        np.testing.assert_allclose(xi, xf, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(li, lf, rtol=1e-12, atol=1e-12 * li[0])
+        assert li[1] < li[0]          # the start is not in the modulus set: the first step moves
+
+
+def test_ip_sequential_order_differs_from_the_averaged_projection():
+    """The reading for several distances: projections in turn. Averaging the
+    distances' projections instead would be the gamma = 1/D step of Eq. (14);
+    the two differ after one iteration."""
+    truth, dists, Hs, y = _ip_problem(D=2, noise=True)
+    xi, li = pr.ip(y, dists, _WL, _PX, 1)
+    xa, _ = pr.fista(y, dists, _WL, _PX, outer=1, inner=2, tau=0.0, gamma=0.5, accelerate=False)
+    # the trace holds F of Eq. (24) summed over both distances
+    np.testing.assert_allclose(li[0], pr.data_term(pr.backprop(list(np.sqrt(y)), Hs), list(np.sqrt(y)), Hs),
+                               rtol=1e-12)
+    assert np.abs(xi - xa).max() > 1e-3
+    # and the sequential order by hand: P_C(P_M2(P_C(P_M1 x0)))
+    sy = np.sqrt(y)
+    x = pr.backprop(list(sy), Hs)
+    for s, H in zip(sy, Hs):
+        u = pr.project_modulus(x, s, H)
+        x = u / np.maximum(1.0, np.abs(u))
+    np.testing.assert_allclose(xi, x, rtol=0, atol=1e-12)
