@@ -19,12 +19,14 @@ per launch) the library's autotuner chose for it: from the saved tuning table
 of this GPU model, or tuned live before the warm-up when the table lacks it.
 The fused kernel performs several iterations per launch, so its real memory
 traffic is far below the per-iteration algorithmic bytes: it is bound by VALU
-issue. `roofline` reports the algorithmic arithmetic operations per second
-against the VALU issue peak without packed FP32 (256 CUs x 4 SIMDs x 16 lanes
-x 2.4 GHz), the measured traffic of the committed PMC profile (when the kernel
-sources are unchanged since it was taken), the FP32 FLOP/s against the
-157.3 TFLOP/s vector peak, and, as `hbm_effective`, the algorithmic bytes per
-second against HBM peak that the metric's "%HBM" refers to.
+issue. `roofline` reports the algorithmic FP32 FLOP/s (FMA = 2) against the
+published 157.3 TFLOP/s vector peak; as secondary fields the algorithmic
+operations per second against the VALU issue peak of this build (no packed
+FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), the measured HBM traffic of the
+committed PMC profile per second against the 8 TB/s peak (the metric's "%HBM",
+when the kernel sources are unchanged since the profile was taken) and the
+bytes an unfused solver would move (57 B per pixel-iteration), whose ratio to
+the HBM peak exceeds 1 because of fusion.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--tuning auto|live|off] [--save-tuning PATH]
 """
@@ -64,6 +66,8 @@ def parse():
     ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
+    ap.add_argument("--cpu-batch-iters", type=int, default=4,
+                    help="iterations per image of the all-cores oracle run over the ragged batch")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (batched ragged workload, ...)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -122,13 +126,64 @@ def _oracle_kind(args):
 
 
 def _cpu_model():
+    """The host CPU as /proc/cpuinfo names it, with family / model / stepping
+    (some hosts report only a short model name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (t.strip() for t in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping", "vendor_id") and k not in info:
+                    info[k] = v
+            if not line.strip() and info:
+                break
     except OSError:
         pass
-    return "unknown"
+    if not info:
+        return "unknown"
+    return (f"{info.get('model name', '?')} (vendor {info.get('vendor_id', '?')}, family {info.get('cpu family', '?')}, "
+            f"model {info.get('model', '?')}, stepping {info.get('stepping', '?')})")
+
+
+def _oracle_image(args):
+    """One image of the ragged batch in a pool worker: (index, seconds of the
+    oracle's solve at `iters` iterations); the worker rebuilds the seeded batch
+    itself, outside the timing."""
+    idx, iters = args
+    import numpy as np
+
+    import synth
+    from oracle import tv
+    global _BATCH3
+    try:
+        _BATCH3
+    except NameError:
+        _BATCH3 = synth.config3(0)
+    d = _BATCH3[idx]
+    t0 = time.perf_counter()
+    tv.fgp(d["b"].astype(np.complex128), d["lam"], iters, d["kind"])
+    return idx, time.perf_counter() - t0
+
+
+def cpu_batched_pool(iters):
+    """The oracle over all 256 ragged images on every host core: a process pool
+    of len(sched_getaffinity) workers, images handed out largest first (LPT by
+    m n), `iters` iterations each (a bounded sample of the 150)."""
+    import multiprocessing as mp
+
+    import synth
+    imgs = synth.config3(0)
+    order = sorted(range(len(imgs)), key=lambda i: -imgs[i]["b"].size)
+    px_it = sum(d["b"].size for d in imgs) * iters
+    workers = len(os.sched_getaffinity(0))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_image, [(i, 0) for i in range(workers)], chunksize=1)   # workers build the batch first
+        t0 = time.perf_counter()
+        pool.map(_oracle_image, [(i, iters) for i in order], chunksize=1)
+        dt = time.perf_counter() - t0
+    return {"value": round(px_it / dt / 1e6, 2), "unit": "Mpixel-iters/s", "cores": workers,
+            "sample": f"256 ragged images (sides 128..1024), {iters} FGP iterations each, "
+                      f"largest first over {workers} worker processes ({dt:.1f} s)"}
 
 
 def cpu_baseline(c, sample_iters):
@@ -160,7 +215,7 @@ def cpu_baseline(c, sample_iters):
                       f"masked image, one kind per worker process ({dtp:.1f} s, slowest worker; numpy float64, "
                       f"single-threaded elementwise; OMP_NUM_THREADS={threads})",
             "single_core": {"value": work / dt1 / 1e6, "cores": 1, "seconds": round(dt1, 2)},
-            "cpu_model": _cpu_model(), "numpy": np.__version__}
+            "host_cores": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model(), "numpy": np.__version__}
 
 
 def timed(fn, reps, torch, stream):
@@ -272,10 +327,48 @@ def bench_pr(ctv, synth, torch, dev, tuner, reps=2):
         lt = lt.cpu().numpy()
         return {f"F_{k}": float(lt[k - 1]) for k in (1, 10, 50, P["outer"]) if k <= len(lt)}
 
+    ks = (10, 50, P["outer"])
+
+    def rmse_trace(run):
+        """Phase RMSE (rad, best global phase removed, Section VI-A) of the
+        estimate after 10, 50 and 100 iterations of `run(k)`."""
+        return {f"rmse_{k}": round(phase_rmse(run(k).cpu().numpy(), truth), 5) for k in ks}
+
+    def fista_run(constraint, accelerate=True):
+        return lambda k: ctv.phase_retrieval(y, P["distances"], P["wavelength"], P["pixel"], tau=P["tau"],
+                                             gamma=P["gamma"], outer=k, inner=P["inner"], constraint=constraint,
+                                             accelerate=accelerate)
+
+    def ip_run(k):
+        return ctv.phase_retrieval_ip(y, P["distances"], P["wavelength"], P["pixel"], iters=k)
+
+    ms_ip = timed(lambda: ip_run(P["outer"]), reps, torch, stream)
+    x0 = ctv.phase_retrieval_ip(y, P["distances"], P["wavelength"], P["pixel"], iters=0)
     return {"workload": "1024^2, D=4, 100 outer x 20 FGP iterations, type-1i, |x|<=1",
             "prox_tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "ms": round(ms, 3), "ms_per_outer_iteration": round(ms / P["outer"], 4),
             "fgp_Mpx_it_s_equiv": round(fgp_px_it / ms / 1e3, 1), "fft2_per_outer_iteration": 2 * len(P["distances"]) + 2,
-            "data_term_fista_vs_ista": {"fista": loss_trace(True), "ista": loss_trace(False)}}
+            "data_term_fista_vs_ista": {"fista": loss_trace(True), "ista": loss_trace(False)},
+            "phase_rmse_fista_vs_ista": {"fista": rmse_trace(fista_run("modulus")),
+                                         "ista": rmse_trace(fista_run("modulus", accelerate=False))},
+            "tv_ctv_ip": {"what": "phase RMSE (rad) on the same measurements: CTV = Algorithm 1 with the "
+                                  "constrained prox (|x| <= 1), TV = the same with C = C^{m x n}, IP = iterative "
+                                  "projections (each distance's modulus set in turn, then |x| <= 1), all from the "
+                                  "back-propagated field",
+                          "backprop_rmse": round(phase_rmse(x0.cpu().numpy(), truth), 5),
+                          "ctv": rmse_trace(fista_run("modulus")), "tv": rmse_trace(fista_run("none")),
+                          "ip": rmse_trace(ip_run), "ip_ms_100_iterations": round(ms_ip, 3),
+                          "ip_fft2_per_iteration": 4 * len(P["distances"])}}
+
+
+def phase_rmse(x, truth):
+    """Phase RMSE with the global phase removed (the error measure of Section
+    VI-A): x is first rotated by the unit phasor of sum(conj(x) * truth), the
+    rotation that brings x closest to the truth in the L2 sense."""
+    import numpy as np
+    c = np.vdot(x, truth)
+    rot = c / abs(c) if abs(c) > 0 else 1.0
+    d = np.angle(x * rot * np.conj(truth))
+    return float(np.sqrt(np.mean(d * d)))
 
 
 def median_ms(fn, reps, torch, stream, before=None):
@@ -394,8 +487,8 @@ def bench_out_of_cache(ctv, synth, torch, dev, tuner, size=8192, iters=48, reps=
             "tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "warm_ms": round(warm, 3),
             "cold_ms": round(cold, 3), "warm_Mpx_it_s": round(px_it / warm / 1e3, 1),
             "cold_Mpx_it_s": round(px_it / cold / 1e3, 1), "computed_px_frac": round(live_px / (size * size), 4),
-            "cold_hbm_effective_frac": round(run_px_it * BYTES_PER_PX_IT_MASKED / (cold * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                             3)}
+            "cold_modelled_unfused_bytes_ratio": round(run_px_it * BYTES_PER_PX_IT_MASKED / (cold * 1e-3) / 1e9
+                                                       / HBM_PEAK_GBS, 3)}
 
 
 def main():
@@ -476,28 +569,48 @@ def main():
     # the profile counts only while it was taken with the same launch configuration
     same_config = bool(pmc) and pmc.get("tuning") == prof_summary.tuning_signature(launch_cfg)
     kp = pmc["kernels"].get(kname) if (same_config and args.size == 2048 and K == 200 and args.fuse == 0) else None
-    roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": round(VALU_OPS_PEAK_GOPS, 1),
-            "unit": "Gop/s", "frac": round(achieved_gops / VALU_OPS_PEAK_GOPS, 4),
+    traffic_gbs = kp["traffic_bytes"] / avg_launch_s / 1e9 if kp else None
+    roof = {"bound": "alu", "achieved": round(achieved_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
             "traffic": kp["traffic_bytes"] if kp else None,
             "kernel": kname, "fused_iters": T, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-            "alg_ops_per_launch": int(alg_ops_launch),
+            "alg_flops_per_launch": int(alg_flops_launch),
+            "flops_per_px_it": {k: FLOPS_PER_PX_IT[k] for k in kinds},
             "live_tiles": [len(kinds) * live_tiles, len(kinds) * all_tiles],
             "computed_px_frac": round(live_px / (m * n), 4),
-            "fp32_flops": {"achieved": round(achieved_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                           "alg_flops_per_launch": int(alg_flops_launch)},
-            "valu_issue_frac": kp["valu_issue_frac"] if kp else None,
-            "traffic_GBs": round(kp["traffic_bytes"] / avg_launch_s / 1e9, 1) if kp else None,
-            "hbm_effective": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                              "alg_bytes_per_launch": int(alg_bytes_launch)}}
+            # the same work against the VALU issue rate of this build (non-packed FP32:
+            # one lane-operation per lane per cycle), counting an FMA, a min, a max or
+            # a reciprocal square root as one operation
+            "valu_issue": {"achieved": round(achieved_gops, 1), "peak": round(VALU_OPS_PEAK_GOPS, 1), "unit": "Gop/s",
+                           "frac": round(achieved_gops / VALU_OPS_PEAK_GOPS, 4),
+                           "ops_per_px_it": {k: OPS_PER_PX_IT[k] for k in kinds},
+                           "alg_ops_per_launch": int(alg_ops_launch),
+                           "pmc_issue_utilisation": kp["valu_issue_frac"] if kp else None},
+            # measured HBM/fabric bytes of the committed PMC profile per launch over the
+            # launch time: the "%HBM peak" of the metric
+            "hbm": ({"achieved": round(traffic_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(traffic_gbs / HBM_PEAK_GBS, 4)} if kp else None),
+            # algorithmic bytes of an unfused iteration (57 B/px-it) per second: what a
+            # one-iteration-per-launch solver would have to move; fusion keeps the real
+            # traffic far below it, so this ratio exceeds 1 and is no bandwidth fraction
+            "modelled_unfused_bytes": {"GBs": round(achieved_gbs, 1), "bytes_per_px_it": BYTES_PER_PX_IT_MASKED,
+                                       "ratio_to_hbm_peak": round(achieved_gbs / HBM_PEAK_GBS, 3),
+                                       "alg_bytes_per_launch": int(alg_bytes_launch)}}
 
+    computed = len(kinds) * live_px * K / (ms_per_step * 1e-3) / 1e6
     out = {"metric": "CTV-FGP Mpixel-iters/s & %HBM peak", "value": round(value, 1),
-           "unit": "Mpixel-iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "unit": "Mpixel-iters/s",
+           # `value` counts every pixel-iteration of the four problems (dense equivalent);
+           # this counts only the pixels of the tiles that run (the others provably keep
+           # a zero dual and x = 0)
+           "computed_Mpx_it_s": round(computed, 1),
+           "hbm_peak_frac": roof["hbm"]["frac"] if roof["hbm"] else None,
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"masked {m}x{n} complex64 CTV denoise, all four TV kinds x {K} FGP iterations, "
-                                  "submitted as one batched plan (one HIP graph)",
+           "config": {"workload": f"masked {m}x{n} complex64 CTV denoise, all four TV kinds x {K} FGP iterations: "
+                                  "the four plain solves submitted together as one batched plan (one HIP graph); "
+                                  "the same solves as four ctv_denoise calls are timed in four_plain_calls",
                       "size": [m, n], "kinds": kinds, "iters": K, "lambda": c["lam"], "alpha": c["alpha"],
                       "constraint": "|x|<=1 + 70% square support",
                       "tiles": "live only: tiles whose output lies where the dual stays zero are not run "
@@ -525,6 +638,7 @@ def main():
         ctv.tune_cache_save(args.save_tuning)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample_iters)
+        out["cpu_baseline"]["ragged_batch_all_cores"] = cpu_batched_pool(args.cpu_batch_iters)
     print(json.dumps(out), flush=True)
 
 

@@ -367,6 +367,23 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
                         float* loss_trace, float* gamma_trace, void* ws, size_t ws_bytes,
                         ctv_stream_t stream);
 
+/* pr_ip - the iterative projection (IP) method that Section VI-A compares
+ * against: K = outer_iters iterations, each projecting the estimate onto the
+ * measured-modulus set of every distance in turn,
+ *   x <- P_C(A_d^H[sqrt(y_d) A_d x / |A_d x|])   for d = 0 .. D-1
+ * (unit phasor where A_d x = 0; P_C of Eq. 26 with C from inner.constraint:
+ * CTV_C_MODULUS is the nonnegative-absorption set of Eq. 25, CTV_C_NONE
+ * projects nothing). With several distances the paper does not fix the order;
+ * the distances are taken in turn. Uses num_meas, distances_host, wavelength,
+ * pixel, outer_iters, init_backprop and inner.constraint (inner must be a
+ * valid ctv_params); tau, gamma and the prox settings are ignored.
+ *   y, x, ws, ws_bytes as in pr_prox_grad.
+ *   loss_trace [K] floats (device) receiving F(x_k) (Eq. 24 summed over d) at
+ *              the start of each iteration, or NULL.
+ * Errors as pr_prox_grad's. */
+ctv_status pr_ip(const pr_params* p, int32_t m, int32_t n, const float* y, float* x, float* loss_trace, void* ws,
+                 size_t ws_bytes, ctv_stream_t stream);
+
 /* Stage entry points of the phase-retrieval path (same conventions).
  * ctv_fft2: 2-D DFT of a complex64 [batch][m][n] array (m, n powers of two in
  *   [2, 4096]); out = sum x exp(-2 pi i (j j'/m + k k'/n)); inverse: + sign and

@@ -92,6 +92,7 @@ _SIGS = {
                                      c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "pr_workspace_size": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_psz]),
     "pr_prox_grad": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "pr_ip": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "ctv_fft2_workspace_size": (c_i32, [c_i32, c_i32, c_i32, c_psz]),
     "ctv_fft2": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, c_vp, c_sz, c_vp]),
     "pr_forward": (c_i32, [ctypes.POINTER(PrParams), c_i32, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]),

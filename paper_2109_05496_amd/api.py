@@ -405,6 +405,23 @@ def phase_retrieval(y, distances, wavelength, pixel, tau=0.01, gamma=0.0, outer=
     return res[0] if len(res) == 1 else tuple(res)
 
 
+def phase_retrieval_ip(y, distances, wavelength, pixel, iters=100, constraint="modulus", x0=None, loss=False):
+    """The iterative projection comparison method of Section VI-A (pr_ip): per
+    iteration, the measured-modulus projection of each distance in turn, each
+    followed by P_C (constraint "modulus": Eq. 25; "none": C = C^{m x n}).
+    y: float32 CUDA [D, m, n]. Starts from the back-propagated field unless x0
+    is given. Returns x (and the data-term trace F(x_k) with loss=True)."""
+    _require_cuda(y, "y", torch.float32)
+    D, m, n = y.shape
+    dev = y.device
+    p, _keep = _pr_params(distances, wavelength, pixel, 0.0, 0.0, iters, 0, "1i", 0.5, constraint, x0 is None, 0, 0)
+    x = torch.empty((m, n), dtype=torch.complex64, device=dev) if x0 is None else x0.clone()
+    lt = torch.empty(max(iters, 1), dtype=torch.float32, device=dev) if loss else None
+    ws = _pr_ws(p, m, n, dev)
+    call("pr_ip", ctypes.byref(p), m, n, _ptr(y), _ptr(x), _ptr(lt), _ptr(ws), ws.numel(), _stream(dev))
+    return (x, lt[:iters]) if loss else x
+
+
 def pr_forward(x, distances, wavelength, pixel):
     _require_cuda(x, "x", torch.complex64)
     m, n = x.shape

@@ -4,10 +4,13 @@
 
 namespace ctv {
 
-enum FftPre { kPreNone = 0, kPreMulH = 1 };
+enum FftPre { kPreNone = 0, kPreMulH = 1, kPreMulConjH = 2 };
 // kPostAccumulateAll: acc (+)= sum over n_acc images of conj(H_img) * transform
 // (the images are looped inside one launch, so there is no race on acc).
-enum FftPost { kPostStore = 0, kPostResidual = 1, kPostAccumulateAll = 2, kPostStep = 3 };
+// kPostReplace: sqrt(y) times the unit phasor of the value (the measured-modulus
+// projection in the sensor plane); kPostProjC: P_C of Eq. (26) (constr).
+enum FftPost { kPostStore = 0, kPostResidual = 1, kPostAccumulateAll = 2, kPostStep = 3, kPostReplace = 4,
+               kPostProjC = 5 };
 
 // One line pass: `lines` lines of length N along the contiguous axis of each
 // batch image. Element p of input image img is in[img * in_stride + p], of
@@ -31,6 +34,7 @@ struct FftArgs {
   double* partial;        // residual loss partials, one per block (and image)
   int accumulate;         // 0: acc = w, 1: acc += w
   int n_acc;              // images summed by kPostAccumulateAll
+  int constr;             // kPostProjC: 0 = C^{m x n} (store), 1 = |x| <= 1
 };
 
 bool fft_size_ok(int v);

@@ -144,14 +144,29 @@ __device__ __forceinline__ void post_op(const FftArgs& a, int img, long long p, 
     if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
     a.out[base + p] = make_float2(ph.x * r, ph.y * r);
     loss += 0.5 * (double)r * (double)r;
-  } else {  // kPostStep
+  } else if (a.post == kPostStep) {
     const float2 z = a.z[p];
     a.out[base + p] = make_float2(fmaf(-a.gamma, v.x, z.x), fmaf(-a.gamma, v.y, z.y));
+  } else if (a.post == kPostReplace) {
+    // keep the phase, impose the measured modulus (unit phasor where the field is 0)
+    const float am = sqrtf(v.x * v.x + v.y * v.y);
+    const float sy = a.sy[(long long)img * a.sy_stride + p];
+    float2 ph = make_float2(1.0f, 0.0f);
+    if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
+    a.out[base + p] = make_float2(ph.x * sy, ph.y * sy);
+  } else {  // kPostProjC: v / max{1, |v|} (Eq. 26)
+    if (a.constr) {
+      const float am = sqrtf(v.x * v.x + v.y * v.y);
+      if (am > 1.0f) v = make_float2(v.x / am, v.y / am);
+    }
+    a.out[base + p] = v;
   }
 }
 
 __device__ __forceinline__ float2 pre_op(const FftArgs& a, int img, long long p, float2 v) {
-  return a.pre == kPreMulH ? cmul(v, a.H[(long long)img * a.H_stride + p]) : v;
+  if (a.pre == kPreNone) return v;
+  const float2 h = a.H[(long long)img * a.H_stride + p];
+  return cmul(v, a.pre == kPreMulH ? h : conjf2(h));
 }
 
 template <int DIR>

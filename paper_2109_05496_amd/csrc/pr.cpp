@@ -138,12 +138,13 @@ ctv_status fft2_to_t(const Ctx& c, const float2* in, float2* out, FftArgs last) 
 // a pass along m (optionally multiplying by Ht on load), then a column pass
 // along n that writes the natural layout, with epilogue `last` (scale 1/(mn)
 // folded in by the caller).
-ctv_status ifft2_from_t(const Ctx& c, const float2* in, const float2* Ht, float2* out, FftArgs last) {
+ctv_status ifft2_from_t(const Ctx& c, const float2* in, const float2* Ht, float2* out, FftArgs last,
+                        int pre = kPreMulH) {
   float2* t1 = c.at(c.L.t1);
   float2* t2 = c.at(c.L.t2);
   FftArgs a = line_args(in, t1, c.at(c.L.tw_m), c.px);
   if (Ht) {
-    a.pre = kPreMulH;
+    a.pre = pre;
     a.H = Ht;
   }
   CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, 1, c.s), "ifft (columns)");
@@ -252,6 +253,51 @@ ctv_status data_term(const Ctx& c, const float2* x, double* out) {
   CTV_TRY(launch_fft_second(r, c.n, c.m, 1, c.D, t2, c.s), "ifft (rows, residual)");
   CTV_TRY(launch_sum_d(part, c.D * residual_blocks(c.m, c.n), 1, 1, out, c.s), "loss");
   return CTV_OK;
+}
+
+// F(x) (Eq. 24 summed over d) into *out (device float): data_term with the
+// loss trace's float reduction.
+ctv_status data_term_f(const Ctx& c, const float2* x, float* out) {
+  double* part = reinterpret_cast<double*>(c.ws + c.L.part);
+  ctv_status st = fft2_to_t(c, x, c.at(c.L.xh), epilogue(kPostStore, 1.0f));
+  if (st) return st;
+  FftArgs a = line_args(c.at(c.L.xh), c.at(c.L.t1), c.at(c.L.tw_m), c.px);
+  a.in_stride = 0;
+  a.pre = kPreMulH;
+  a.H = c.Ht(0);
+  a.H_stride = c.px;
+  CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, c.D, c.s), "ifft (columns)");
+  FftArgs r = line_args(c.at(c.L.t1), c.at(c.L.t2), c.at(c.L.tw_n), c.px);
+  r.post = kPostResidual;
+  r.scale = 1.0f / (float)((double)c.m * c.n);
+  r.sy = c.sy(0);
+  r.sy_stride = c.px;
+  r.partial = part;
+  CTV_TRY(launch_fft_second(r, c.n, c.m, 1, c.D, c.at(c.L.t2), c.s), "ifft (rows, residual)");
+  CTV_TRY(launch_loss_final(part, c.D * residual_blocks(c.m, c.n), out, c.s), "loss");
+  return CTV_OK;
+}
+
+// x <- P_C(A_d^H [sqrt(y_d) A_d x / |A_d x|]): the measured-modulus projection
+// of distance d followed by the projection onto C (one step of the iterative
+// projection method), four 2-D transforms with the pointwise work in their
+// first / last passes.
+ctv_status ip_step(const Ctx& c, int d, int constr, const float2* x, float2* out) {
+  const float inv = 1.0f / (float)((double)c.m * c.n);
+  float2* xh = c.at(c.L.xh);
+  float2* u = c.at(c.L.v);
+  ctv_status st = fft2_to_t(c, x, xh, epilogue(kPostStore, 1.0f));
+  if (st) return st;
+  FftArgs rep = epilogue(kPostReplace, inv);
+  rep.sy = c.sy(d);
+  rep.sy_stride = 0;
+  st = ifft2_from_t(c, xh, c.Ht(d), u, rep, kPreMulH);
+  if (st) return st;
+  st = fft2_to_t(c, u, xh, epilogue(kPostStore, 1.0f));
+  if (st) return st;
+  FftArgs pc = epilogue(kPostProjC, inv);
+  pc.constr = constr;
+  return ifft2_from_t(c, xh, c.Ht(d), out, pc, kPreMulConjH);
 }
 
 Ctx make_ctx(const pr_params* p, int m, int n, void* ws, ctv_stream_t stream) {
@@ -460,6 +506,44 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
     const float b = p->accelerate ? (float)((t - 1.0) / tn) : 0.0f;
     CTV_TRY(launch_fista(xcur, xprev, z, b, c.px, c.s), "fista step");
     t = tn;
+  }
+  CTV_TRY(launch_copy_c(xcur, reinterpret_cast<float2*>(x), c.px, c.s), "copy");
+  return CTV_OK;
+}
+
+ctv_status pr_ip(const pr_params* p, int32_t m, int32_t n, const float* y, float* x, float* loss_trace, void* ws,
+                 size_t ws_bytes, ctv_stream_t stream) {
+  ctv_status st = validate_pr(p, m, n, false);
+  if (st) return st;
+  st = validate_params(&p->inner);
+  if (st) return st;
+  if (p->outer_iters < 0) return fail(CTV_ERR_INVALID_ARG, "outer_iters must be >= 0");
+  if (!y || !x || !ws) return fail(CTV_ERR_INVALID_ARG, "y, x and ws must be non-NULL");
+  Ctx c = make_ctx(p, m, n, ws, stream);
+  if (ws_bytes < c.L.total) return fail(CTV_ERR_WORKSPACE, "workspace too small");
+  st = build_tables(c, p, y);
+  if (st) return st;
+  float2* xcur = c.at(c.L.xcur);
+  if (p->init_backprop) {
+    float2* syc = c.at(c.L.syc);
+    float2* acc = c.at(c.L.acc);
+    CTV_TRY(launch_sqrt_y(y, c.atf(c.L.sy), syc, (long long)c.D * c.px, c.s), "sqrt(y)");
+    st = accumulate_spectra(c, syc, acc);
+    if (st) return st;
+    st = ifft2_from_t(c, acc, nullptr, xcur, epilogue(kPostStore, 1.0f / (float)((double)m * n) / (float)c.D));
+    if (st) return st;
+  } else {
+    CTV_TRY(launch_copy_c(reinterpret_cast<const float2*>(x), xcur, c.px, c.s), "copy");
+  }
+  for (int k = 0; k < p->outer_iters; ++k) {
+    if (loss_trace) {
+      st = data_term_f(c, xcur, loss_trace + k);
+      if (st) return st;
+    }
+    for (int d = 0; d < c.D; ++d) {
+      st = ip_step(c, d, p->inner.constraint, xcur, xcur);
+      if (st) return st;
+    }
   }
   CTV_TRY(launch_copy_c(xcur, reinterpret_cast<float2*>(x), c.px, c.s), "copy");
   return CTV_OK;

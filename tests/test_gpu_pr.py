@@ -231,3 +231,55 @@ def test_non_square_problem_matches_oracle(m, n):
     xo, _ = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 1, 7, 0.02, 0.4, "2i")
     assert rel(xg, xo) <= 1e-5, rel(xg, xo)
     assert elem(xg, xo) <= ELEM_TOL, elem(xg, xo)
+
+
+# ---------------------------------------------------------------------------
+# Iterative projection (IP) comparison method of Section VI-A (pr_ip).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("iters,constraint,shape,D", [(1, "modulus", (128, 128), 2), (3, "modulus", (128, 128), 2),
+                                                      (3, "none", (128, 128), 2), (2, "modulus", (64, 128), 3),
+                                                      (3, "modulus", (128, 32), 1)])
+def test_ip_iterations_match_oracle(iters, constraint, shape, D):
+    m, n = shape
+    big = synth.config5_object(seed=4, size=max(m, n), n_shapes=10, sigma_px=2.0)
+    truth = big[:m, :n]
+    dists = P5["distances"][:D]
+    Hs = [opr.transfer(m, n, d, P5["wavelength"], P5["pixel"]) for d in dists]
+    rng = np.random.default_rng(11)
+    y = np.stack([synth.poisson_measure(np.abs(opr.A(truth, H)) ** 2, P5["photons"], rng) for H in Hs])
+    x, lt = ctv().phase_retrieval_ip(dev(y), dists, P5["wavelength"], P5["pixel"], iters=iters, constraint=constraint,
+                                     loss=True)
+    xo, lo = opr.ip(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], iters, constraint=constraint)
+    xg = x.cpu().numpy()
+    print("ip", iters, constraint, shape, D, "rel-L2", rel(xg, xo), "elementwise", elem(xg, xo))
+    assert rel(xg, xo) <= 1e-5, rel(xg, xo)
+    assert elem(xg, xo) <= ELEM_TOL, elem(xg, xo)
+    # (with one distance the back-propagated start has F = 0 up to rounding: an absolute
+    # floor on the scale of the data, sum(y))
+    np.testing.assert_allclose(lt.cpu().numpy(), lo, rtol=1e-4, atol=1e-7 * float(np.sum(y)))
+    if constraint == "modulus":
+        assert float(x.abs().max()) <= 1 + 1e-6
+
+
+def test_ip_noise_free_truth_stays_fixed():
+    m = 128
+    truth = synth.config5_object(seed=6, size=m, n_shapes=10, sigma_px=2.0).astype(np.complex64)
+    dists = P5["distances"][:3]
+    Hs = [opr.transfer(m, m, d, P5["wavelength"], P5["pixel"]) for d in dists]
+    y = np.stack([np.abs(opr.A(truth.astype(np.complex128), H)) ** 2 for H in Hs]).astype(np.float32)
+    x = ctv().phase_retrieval_ip(dev(y), dists, P5["wavelength"], P5["pixel"], iters=3, x0=dev(truth)).cpu().numpy()
+    assert rel(x, truth) <= 2e-6, rel(x, truth)
+
+
+def test_ip_one_distance_equals_prox_gradient_with_projection_prox():
+    """One distance: an IP iteration is the proximal gradient step with gamma = 1
+    and a prox of P_C alone (tau = 0), computed here by the other entry point."""
+    truth, Hs, y = small_problem(m=128, D=1, seed=12)
+    dists = P5["distances"][:1]
+    rng = np.random.default_rng(13)
+    x0 = (1.3 * truth * np.exp(0.7j) + 0.2 * (rng.standard_normal(truth.shape)
+                                              + 1j * rng.standard_normal(truth.shape))).astype(np.complex64)
+    xi = ctv().phase_retrieval_ip(dev(y), dists, P5["wavelength"], P5["pixel"], iters=3, x0=dev(x0)).cpu().numpy()
+    xf = ctv().phase_retrieval(dev(y), dists, P5["wavelength"], P5["pixel"], tau=0.0, gamma=1.0, outer=3, inner=2,
+                               accelerate=False, x0=dev(x0)).cpu().numpy()
+    assert rel(xi, xf) <= 1e-6, rel(xi, xf)
