@@ -94,9 +94,12 @@ typedef struct {
   int32_t fuse;         /* at most this many iterations fused per kernel launch, 1..16 (a run is
                            split into the fewest launches, iterations spread evenly); 0 = automatic */
   int32_t tile_waves;   /* tile shape (tuning): 0 = automatic; 4, 8 or 16 wave64s per workgroup in
-                           the column-register tile; -1 = the LDS-staged tile (4 waves) */
+                           the column-register tile; -1 = the LDS-staged tile (4 waves); -2 = the
+                           row-sweep tile (8 waves sweeping down a 64-column strip one iteration
+                           behind each other, no vertical halo; at most 10 fused iterations) */
   int32_t tile_rows;    /* rows per thread: 0 = automatic; column tile 4 or 8 (with waves 4: 8 only);
-                           LDS tile 4, 8 or 16 */
+                           LDS tile 4, 8 or 16; row-sweep tile: output rows of a tile, a multiple of 4 in
+                           [16, 1024] */
   int32_t method;       /* CTV_M_FGP: Algorithm 2 with the t_k extrapolation; CTV_M_GP: the
                            unaccelerated gradient projection of Eq. (21), r_k = q_{k-1} */
   int32_t schedule;     /* CTV_S_AUTO, CTV_S_STEPS (one kernel launch per fused step) or
@@ -269,8 +272,8 @@ ctv_status ctv_batched_plan_tiling(const ctv_batched_plan* plan, int32_t* fuse_o
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t fuse;        /* at most this many iterations fused per launch */
-  int32_t tile_waves;  /* wave64s per workgroup */
-  int32_t tile_rows;   /* rows per thread */
+  int32_t tile_waves;  /* as ctv_params.tile_waves */
+  int32_t tile_rows;   /* as ctv_params.tile_rows */
   float ms;            /* median time of one call, milliseconds */
 } ctv_tuning;
 

@@ -98,12 +98,14 @@ std::vector<Candidate> candidates(bool batched, int iters, bool single_tile) {
   struct Shape {
     int waves, rows, tmax;
   };
-  static const Shape plain_shapes[] = {{8, 8, 12}, {8, 4, 8}, {4, 8, 8}, {16, 4, 10}};
-  static const Shape batched_shapes[] = {{8, 8, 12}, {8, 4, 8}, {16, 4, 10}};
+  // (kSweepShape, SH): the row-sweep tile with segments of SH output rows
+  static const Shape plain_shapes[] = {{8, 8, 12}, {8, 4, 8}, {4, 8, 8}, {16, 4, 10},
+                                       {kSweepShape, 144, kSweepMaxFuse}};
+  static const Shape batched_shapes[] = {{8, 8, 12}, {8, 4, 8}, {16, 4, 10}, {kSweepShape, 144, kSweepMaxFuse}};
   std::vector<Candidate> out;
   const int kcap = std::max(1, iters);
   auto add_shape = [&](const Shape& s) {
-    const int rows = s.waves * s.rows;
+    const int rows = TileShape{s.waves, s.rows}.rows();
     const int hmax = (std::min(64, rows) - 1) / 2;
     const int tmax = std::min({s.tmax, hmax - 1, kMaxFuse, kcap});
     // an image inside one 8 x 8 tile runs in the single-tile kernel, which
@@ -424,7 +426,7 @@ ctv_status ctv_tune_cache_load(const char* path) {
     const unsigned long long k = ok ? std::strtoull(key.c_str(), &end, 16) : 0;
     // range and integrality are checked on the doubles, before any conversion
     auto small_int = [](double v, int lo, int hi) { return v >= lo && v <= hi && v == std::floor(v); };
-    const bool nums = small_int(T, 1, kMaxFuse) && small_int(w, 1, 64) && small_int(r, 1, 64);
+    const bool nums = small_int(T, 1, kMaxFuse) && (small_int(w, 1, 64) || w == kSweepShape) && small_int(r, 1, 256);
     const TileShape ts{nums ? (int)w : 0, nums ? (int)r : 0};
     if (!ok || key.empty() || (end && *end) || arch.empty() || !nums || !valid_tile_shape(ts))
       return fail(CTV_ERR_INVALID_ARG, std::string(path) + ":" + std::to_string(lineno) + ": malformed tuning entry");

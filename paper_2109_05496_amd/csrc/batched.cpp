@@ -92,6 +92,7 @@ void fill_args(ctv_batched_plan* p) {
     a.T = p->tiling.T;
     a.live = p->nflags ? p->d_lists + p->step_offset[s] : nullptr;
     a.live_count = p->nflags ? p->d_counts + s : nullptr;
+    a.sweep_rows = p->tiling.shape.sweep() ? p->tiling.shape.rows_per_thread : 0;
   }
   BatchScanArgs& sa = p->scan_args;
   sa.images = p->d_images;
@@ -103,6 +104,7 @@ void fill_args(ctv_batched_plan* p) {
   sa.x = p->x;
   sa.flags = p->d_flags;
   sa.rows = p->tiling.shape.rows();
+  sa.sweep_oh = p->tiling.shape.sweep() ? p->tiling.shape.rows_per_thread : 0;
   BatchCompactArgs& ca = p->compact_args;
   ca.tiles = p->d_tiles;
   ca.step_offset = p->d_step_offset;
@@ -229,11 +231,10 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
   p->func = fgp_batched_kernel_ptr(common->constraint, tl.shape);
   if (!p->func) {
     release(p);
-    return fail(CTV_ERR_UNSUPPORTED, "the batched kernel supports the 8x8, 8x4 and 16x4 column tiles");
+    return fail(CTV_ERR_UNSUPPORTED, "the batched kernel supports the 8x8, 8x4 and 16x4 column tiles and the row sweep");
   }
-  p->block = tl.shape.waves * 64;
+  p->block = tl.shape.threads();
   const int T = tl.T;
-  const int rows = tl.shape.rows();
 
   // per-step tile lists; tiles of images with a support (and iterations) get a
   // live flag of their (image, tiling) pair
@@ -252,7 +253,7 @@ ctv_status ctv_batched_plan_create(const ctv_image_desc* descs, int32_t count, c
       const int Ti = std::min(T, b.iters - k0);
       const bool last = (k0 + Ti == b.iters);
       const int H = std::max(1, Ti + (last ? 1 : 0));
-      const int ow = 64 - 2 * H, oh = rows - 2 * H;
+      const int ow = 64 - 2 * H, oh = tl.shape.out_rows(H);
       const int tx = (b.n + ow - 1) / ow, ty = (b.m + oh - 1) / oh;
       int base = -1;
       if (b.support_offset >= 0 && b.iters > 0) {

@@ -90,6 +90,7 @@ float step_of(float lam) {
 }
 
 bool valid_tile_shape(const TileShape& ts) {
+  if (ts.sweep()) return ts.rows_per_thread >= 16 && ts.rows_per_thread <= 1024 && ts.rows_per_thread % 4 == 0;
   if (ts.waves > 0)
     return (ts.waves == 4 && ts.rows_per_thread == 8) ||
            ((ts.waves == 8 || ts.waves == 16) && (ts.rows_per_thread == 4 || ts.rows_per_thread == 8));
@@ -101,6 +102,7 @@ void clamp_fuse(Tiling* t, int iters) {
   // the epilogue launch needs H = T + 1.
   const int hmax = (std::min(64, t->shape.rows()) - 1) / 2;
   t->T = std::min(t->T, hmax - 1);
+  if (t->shape.sweep()) t->T = std::min(t->T, kSweepMaxFuse);
   if (iters > 0) t->T = std::min(t->T, iters);
   t->T = std::max(t->T, 1);
 }
@@ -114,9 +116,10 @@ ctv_status choose_tiling(const ctv_params* p, int m, int n, int batch, Tiling* o
   t.T = 8;
   if (p->tile_waves != 0 || p->tile_rows != 0) {
     if (p->tile_waves == 0 || p->tile_rows == 0) return fail(CTV_ERR_INVALID_ARG, "tile_waves and tile_rows must be set together");
-    t.shape.waves = p->tile_waves < 0 ? 0 : p->tile_waves;
+    t.shape.waves = p->tile_waves == -1 ? 0 : p->tile_waves;   // -1: LDS tile; kSweepShape: row sweep
     t.shape.rows_per_thread = p->tile_rows;
-    if (p->tile_waves < -1 || !valid_tile_shape(t.shape)) return fail(CTV_ERR_INVALID_ARG, "unsupported tile shape");
+    if (p->tile_waves < kSweepShape || !valid_tile_shape(t.shape))
+      return fail(CTV_ERR_INVALID_ARG, "unsupported tile shape");
   } else if (use_tuned && p->fuse == 0) {
     Tiling tuned;
     if (tuned_lookup(plain_tune_key(p, batch, m, n), &tuned) && valid_tile_shape(tuned.shape)) t = tuned;
@@ -175,15 +178,16 @@ ctv_status fgp_launch(const ctv_params* p, const Tiling& tl, int cb, int m, int 
   a.x = x;
   a.r_hist = r_hist;
   a.r_hist_stride = r_hist_stride;
-  if (live && (tl.shape.waves <= 0 || r_hist))
-    return fail(CTV_ERR_INVALID_ARG, "internal: live-tile lists need the column tiles");
+  if (live && ((tl.shape.waves <= 0 && !tl.shape.sweep()) || r_hist))
+    return fail(CTV_ERR_INVALID_ARG, "internal: live-tile lists need the column or row-sweep tiles");
   a.live = live;
   a.T = Tl;
   a.halo = std::max(1, Tl + (x ? 1 : 0));
   for (int i = 0; i < kMaxFuse; ++i) a.beta[i] = (i < Tl) ? beta[(size_t)(k + 1 + i)] : 0.0f;
-  const int rows = tl.shape.rows();
+  const int oh = tl.shape.out_rows(a.halo);
   a.tiles_x = (n + (64 - 2 * a.halo) - 1) / (64 - 2 * a.halo);
-  a.tiles_y = (m + (rows - 2 * a.halo) - 1) / (rows - 2 * a.halo);
+  a.tiles_y = (m + oh - 1) / oh;
+  a.sweep_rows = tl.shape.sweep() ? tl.shape.rows_per_thread : 0;
   hipError_t e = launch_fgp_plain(a, p->tv_kind, p->constraint, tl.shape, cb, s);
   if (e != hipSuccess) return hip_fail(e, "fgp launch");
   return CTV_OK;
@@ -229,7 +233,7 @@ ctv_status ctv_tiling(const ctv_params* p, int32_t batch, int32_t m, int32_t n, 
   if (st) return st;
   if (fuse_out) *fuse_out = t.T;
   if (region_rows_out) *region_rows_out = t.shape.rows();
-  if (tile_waves_out) *tile_waves_out = t.shape.waves > 0 ? t.shape.waves : -1;
+  if (tile_waves_out) *tile_waves_out = (t.shape.waves > 0 || t.shape.sweep()) ? t.shape.waves : -1;
   if (tile_rows_out) *tile_rows_out = t.shape.rows_per_thread;
   return CTV_OK;
 }
@@ -376,7 +380,7 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
       // writes x stores x = 0 in its skipped tiles. Launches into checkpoint
       // slots or a caller's state buffer run every tile. Results are bitwise
       // those of running every tile.
-      const bool may_skip = support && !state_in && tl.shape.waves > 0;
+      const bool may_skip = support && !state_in && (tl.shape.waves > 0 || tl.shape.sweep());
       int slot_h[kLiveSlots], slot_x[kLiveSlots], used = 0;
       bool zeroed = false;
       const size_t slot_ints = 2 * live_cap(m, n) + 1;
@@ -396,8 +400,8 @@ ctv_status ctv_denoise(const ctv_params* p, int32_t batch, int32_t m, int32_t n,
         const bool dst_ws = !dst || dst == bufA + st_off || dst == bufB + st_off;
         if (may_skip && dst_ws) {
           const int H = std::max(1, Tl + (last ? 1 : 0));
-          const int rows = tl.shape.rows();
-          const int OW = 64 - 2 * H, OH = rows - 2 * H;
+          const int OW = 64 - 2 * H, OH = tl.shape.out_rows(H);
+          const int rows = OH + 2 * H;   // region rows of the scan's tiling
           const long long tiles = (long long)((n + OW - 1) / OW) * ((m + OH - 1) / OH);
           int slot = -1;
           for (int i = 0; i < used; ++i)

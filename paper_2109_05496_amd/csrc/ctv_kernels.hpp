@@ -26,8 +26,9 @@ struct FgpPlainArgs {
   float* r_hist;         // 8 x 8 column tile only: states [T][chunk][2][m][n][4] whose plane 1
                          // receives r after each fused iteration (output pixels), or nullptr
   long long r_hist_stride;  // floats from one iteration's state to the next
-  const int* live;       // column tiles only: [0] = L, [1 .. L] = the tiles (of one image) to run, or
-                         // nullptr for all; the grid stays one workgroup per tile of the chunk
+  const int* live;       // column and row-sweep tiles: [0] = L, [1 .. L] = the tiles (of one image) to
+                         // run, or nullptr for all; the grid stays one workgroup per tile of the chunk
+  int sweep_rows;        // row-sweep tile: output rows of a tile (a segment); 0 otherwise
 };
 
 // Persistent dataflow form of the plain path (8 x 8 column tile): one launch
@@ -113,7 +114,8 @@ struct BatchScanArgs {
   float* st1;
   float* x;
   int* flags;
-  int rows;                 // region rows of the tile shape
+  int rows;                 // region rows of the tile shape (column tiles)
+  int sweep_oh;             // row-sweep tile: output rows of a tile (region rows then sweep_oh + 2 halo); 0 otherwise
 };
 
 struct BatchCompactArgs {
@@ -141,22 +143,33 @@ struct FgpBatchedArgs {
   int T;                    // iterations fused in this step
   const int* live;          // this step's tiles to run (indices into tiles) or nullptr = all
   const int* live_count;
+  int sweep_rows;           // row-sweep tile: output rows of a tile; 0 for the column tiles
 };
 
 // Tile shape of the plain kernels: waves > 0 selects the column-register tile
 // (waves wave64s, rows_per_thread consecutive rows each); waves == 0 selects the
-// LDS tile with 4 waves and rows_per_thread * 4 region rows.
+// LDS tile with 4 waves and rows_per_thread * 4 region rows; waves ==
+// kSweepShape the row-sweep tile with rows_per_thread output rows per tile.
 struct TileShape {
   int waves;
   int rows_per_thread;
-  int rows() const { return (waves > 0 ? waves : 4) * rows_per_thread; }
+  bool sweep() const { return waves == kSweepShape; }
+  // region rows without the halo (column / LDS tiles) or output rows (row sweep)
+  int rows() const { return sweep() ? rows_per_thread : (waves > 0 ? waves : 4) * rows_per_thread; }
+  // output rows of a tile at halo H
+  int out_rows(int H) const { return sweep() ? rows_per_thread : rows() - 2 * H; }
+  // workgroup size
+  int threads() const { return sweep() ? kSweepWaves * 64 : (waves > 0 ? waves : 4) * 64; }
 };
 bool valid_tile_shape(const TileShape& ts);
-// Batched kernel for a column-register tile shape (8x8, 8x4 or 16x4), else nullptr.
+// Batched kernel for a column-register tile shape (8x8, 8x4 or 16x4) or the
+// row-sweep tile, else nullptr.
 const void* fgp_batched_kernel_ptr(int constr, const TileShape& ts);
 
 hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const TileShape& ts, int batch,
                             hipStream_t s);
+hipError_t launch_fgp_sweep(const FgpPlainArgs& a, int kind, int constr, int batch, hipStream_t s);
+const void* fgp_sweep_batched_kernel_ptr(int constr);
 
 hipError_t launch_zero_f4(float* p, long long count_f4, hipStream_t s);
 

@@ -8,6 +8,14 @@ enum Constr { C_NONE = 0, C_MOD = 1 };
 
 constexpr int kMaxFuse = 16;
 
+// Row-sweep tile (fgp_sweep.hip): 8 waves, 4-row windows per wave, at most 10
+// fused iterations (its LDS ring holds T + 2 rows per lane), segments of
+// kSweepSegRows[i] output rows. TileShape::waves == kSweepShape selects it.
+constexpr int kSweepWaves = 8;
+constexpr int kSweepRows = 4;
+constexpr int kSweepMaxFuse = 10;
+constexpr int kSweepShape = -2;
+
 // Smallest positive lambda accepted: 1/(8 lambda^2) (the backward's step
 // derivative) and the squared dual norms stay far from float32 overflow.
 constexpr float kMinLambda = 1e-12f;

@@ -20,27 +20,14 @@
 
 #include "ctv_device.hpp"
 #include "ctv_kernels.hpp"
+#include "ctv_tile.hpp"
 
 namespace ctv {
 
-constexpr int kRW = 64;
+
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-struct TileJob {
-  const float2* b;       // image (m x n)
-  const uint8_t* mask;   // image support or nullptr
-  const float4* st_in;   // [2][m][n] (q plane, r plane) or nullptr = cold start
-  float4* st_out;        // [2][m][n] or nullptr
-  float2* x;             // Eq. (18) output or nullptr
-  int m, n;
-  int tx, ty;
-  float lam, c;
-  Radii R;
-  int T;
-  float4* r_hist;          // r after each fused iteration (plane 1 of consecutive states), or nullptr
-  long long hist_stride;   // float4 elements from one iteration's state to the next
-};
 
 template <int KIND, int CONSTR, bool MASK, int RH>
 __device__ __forceinline__ void fgp_tile(const TileJob& J, const int H, const float* sBeta,
@@ -156,12 +143,6 @@ __device__ __forceinline__ void fgp_tile(const TileJob& J, const int H, const fl
 // boundary between two waves go through LDS (one row of (r1,s1) down, one row
 // of y up per iteration). Same arithmetic, same halo rule as above.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float lane_from_left(float v) {   // lane i <- lane i-1 (lane 0 <- 0)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float lane_from_right(float v) {  // lane i <- lane i+1 (lane 63 <- 0)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
-}
 
 // Dual-state element access. COH = true (the dataflow kernel) uses 64-bit
 // agent-scope atomic accesses, which are coherent across the XCDs' separate
@@ -188,12 +169,6 @@ __device__ __forceinline__ void st_state(float4* p, float4 v) {
   __hip_atomic_store(u + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bits [max(a, 0), min(b, n)) set: the rows i of a wave with a <= i < b.
-__device__ __forceinline__ unsigned row_bits(int a, int b, int n) {
-  a = min(max(a, 0), n);
-  b = min(max(b, 0), n);
-  return ((1u << b) - 1u) & ~((1u << a) - 1u);
-}
 
 // BORDER = false is the fast path for tiles whose region lies at least one
 // pixel inside the image on every side: no neighbour there leaves the image, so
@@ -733,7 +708,8 @@ __global__ __launch_bounds__(kScanWaves * 64) void batched_scan_kernel(BatchScan
   const BatchGeom G = a.geoms[a.geo_of[f]];
   const BatchImage D = a.images[G.image];
   const long long st = 2 * D.offset * 4;  // float offset of the image's state
-  const bool live = scan_tile(a.support + D.support_offset, D.m, D.n, G.halo, a.rows, G.tiles_x,
+  const int rows = a.sweep_oh > 0 ? a.sweep_oh + 2 * G.halo : a.rows;
+  const bool live = scan_tile(a.support + D.support_offset, D.m, D.n, G.halo, rows, G.tiles_x,
                               f - G.flag_base, G.zero_st != 0, a.st0 + st, a.st1 + st,
                               G.zero_x ? a.x + 2 * D.offset : nullptr, 1, sLive);
   if (threadIdx.x == 0) a.flags[f] = live ? 1 : 0;
@@ -974,6 +950,7 @@ static hipError_t launch_col_kind(const FgpPlainArgs& a, int constr, bool mask, 
 
 hipError_t launch_fgp_plain(const FgpPlainArgs& a, int kind, int constr, const TileShape& ts, int batch,
                             hipStream_t s) {
+  if (ts.sweep()) return launch_fgp_sweep(a, kind, constr, batch, s);
   const int nblocks = a.tiles_x * a.tiles_y * batch;
   const bool mask = a.mask != nullptr;
   if (ts.waves > 0) {
@@ -1054,6 +1031,7 @@ hipError_t launch_fgp_flow(const FgpFlowArgs& a, int kind, int constr, hipStream
 }
 
 const void* fgp_batched_kernel_ptr(int constr, const TileShape& ts) {
+  if (ts.sweep()) return fgp_sweep_batched_kernel_ptr(constr);
 #define CTV_BK(NW_, P_)                                                                      \
   if (ts.waves == NW_ && ts.rows_per_thread == P_)                                           \
     return constr == C_MOD ? reinterpret_cast<const void*>(&fgp_batched_kernel<C_MOD, NW_, P_>) \
