@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--fuse", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
+    ap.add_argument("--pr-oracle", action="store_true",
+                    help="also run the full phase-retrieval problem in the FP64 oracle (minutes) and report the "
+                         "GPU's end-to-end error against it")
     ap.add_argument("--cpu-batch-iters", type=int, default=4,
                     help="iterations per image of the all-cores oracle run over the ragged batch")
     ap.add_argument("--no-extras", action="store_true",
@@ -216,6 +219,33 @@ def cpu_baseline(c, sample_iters):
                       f"single-threaded elementwise; OMP_NUM_THREADS={threads})",
             "single_core": {"value": work / dt1 / 1e6, "cores": 1, "seconds": round(dt1, 2)},
             "host_cores": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model(), "numpy": np.__version__}
+
+
+def pr_end_to_end(ctv, synth, torch, dev):
+    """The full phase-retrieval run (1024^2, D = 4, 100 x 20, FISTA) on the GPU
+    and in the FP64 oracle on the same measurements (simulated with the
+    oracle's propagator): the end-to-end relative L2 error of x, and the
+    oracle's time on one core. Minutes of CPU work, so only with --pr-oracle."""
+    import numpy as np
+    from oracle import pr as opr
+    P = synth.PR_DEFAULTS
+    truth = synth.config5_object(seed=0)
+    m = truth.shape[0]
+    Hs = [opr.transfer(m, m, d, P["wavelength"], P["pixel"]) for d in P["distances"]]
+    rng = np.random.default_rng(0)
+    y = np.stack([synth.poisson_measure(np.abs(opr.A(truth, H)) ** 2, P["photons"], rng) for H in Hs])
+    xg = ctv.phase_retrieval(torch.as_tensor(y).to(dev), P["distances"], P["wavelength"], P["pixel"], tau=P["tau"],
+                             gamma=P["gamma"], outer=P["outer"], inner=P["inner"]).cpu().numpy()
+    t0 = time.perf_counter()
+    xo, _ = opr.fista(y.astype(np.float64), P["distances"], P["wavelength"], P["pixel"], P["outer"], P["inner"],
+                      P["tau"], P["gamma"])
+    dt = time.perf_counter() - t0
+    px_it = m * m * P["outer"] * P["inner"]
+    return {"workload": "1024^2, D=4, 100 outer x 20 FGP iterations (FISTA), same measurements on both sides",
+            "rel_l2_x": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+            "elementwise_x": float(np.abs(xg - xo).max() / np.abs(xo).max()),
+            "phase_rmse_gpu": phase_rmse(xg, truth), "phase_rmse_oracle": phase_rmse(xo, truth),
+            "oracle_seconds": round(dt, 1), "oracle_fgp_Mpx_it_s_equiv": round(px_it / dt / 1e6, 2), "cores": 1}
 
 
 def timed(fn, reps, torch, stream):
@@ -639,6 +669,8 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_sample_iters)
         out["cpu_baseline"]["ragged_batch_all_cores"] = cpu_batched_pool(args.cpu_batch_iters)
+        if args.pr_oracle:
+            out["cpu_baseline"]["phase_retrieval_end_to_end"] = pr_end_to_end(ctv, synth, torch, dev)
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,8 @@
 """GPU tests of the phase-retrieval path: the Stockham FFT, the angular-spectrum
 propagator (Eq. 23), the data-term gradient (Eq. 27) and FISTA (Algorithm 1)
 with the FGP prox, against the FP64 oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -133,6 +135,34 @@ def test_config5_full_run():
     assert loss[-1] < 0.5 * loss[0]
     assert e1 < e0
     assert np.all(np.abs(x) <= 1 + 1e-5)
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("CTV_SLOW") != "1", reason="minutes of FP64 oracle work; set CTV_SLOW=1")
+def test_config5_end_to_end_against_oracle():
+    """The full phase-retrieval run (1024^2, D = 4, 100 outer x 20 inner
+    iterations, FISTA and ISTA) against the FP64 oracle run on the same
+    measurements: the relative L2 error of x after 100 nonconvex outer
+    iterations, its element-wise error, the data-term trace and the phase RMSE
+    are printed; the bar of the per-stage tests (1e-5) is asserted on the end
+    result as well."""
+    truth = synth.config5_object(seed=0)
+    m = truth.shape[0]
+    Hs = [opr.transfer(m, m, d, P5["wavelength"], P5["pixel"]) for d in P5["distances"]]
+    rng = np.random.default_rng(0)
+    y = np.stack([synth.poisson_measure(np.abs(opr.A(truth, H)) ** 2, P5["photons"], rng) for H in Hs])
+    for acc in (True, False):
+        x, lt = ctv().phase_retrieval(dev(y), P5["distances"], P5["wavelength"], P5["pixel"], tau=P5["tau"],
+                                      gamma=P5["gamma"], outer=P5["outer"], inner=P5["inner"], accelerate=acc,
+                                      loss=True)
+        xg, lt = x.cpu().numpy(), lt.cpu().numpy().astype(np.float64)
+        xo, lo = opr.fista(y.astype(np.float64), P5["distances"], P5["wavelength"], P5["pixel"], P5["outer"],
+                           P5["inner"], P5["tau"], P5["gamma"], accelerate=acc)
+        print("config5 end to end", "FISTA" if acc else "ISTA", "rel-L2", rel(xg, xo), "elementwise", elem(xg, xo),
+              "loss trace max rel", float(np.max(np.abs(lt - lo) / lo)), "phase RMSE", opr.phase_rmse(xg, truth),
+              opr.phase_rmse(xo, truth))
+        assert rel(xg, xo) <= 1e-5 and elem(xg, xo) <= ELEM_TOL
+        np.testing.assert_allclose(lt, lo, rtol=1e-5)
 
 
 def test_config5_fista_beats_ista():
