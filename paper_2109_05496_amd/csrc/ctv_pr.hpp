@@ -47,6 +47,11 @@ hipError_t launch_transpose(const float2* in, float2* out, int R, int C, int bat
 // epilogue a transpose into tmp (N * W elements per image) and a line pass.
 hipError_t launch_fft_second(FftArgs a, int N, long long W, int dir, int batch, float2* tmp, hipStream_t s);
 int fft_second_blocks(int N, long long W);
+// Inverse DFT of every N-long column of [N][W] images (N >= 32), the Eq. (27)
+// residual (a.sy, a.sy_stride, a.scale, loss partials in a.partial with
+// fft_second_blocks(N, W) blocks per image), forward DFT back; out keeps the
+// [N][W] layout.
+hipError_t launch_fft_roundtrip(FftArgs a, int N, long long W, int batch, hipStream_t s);
 hipError_t launch_twiddles(float2* tw, int N, hipStream_t s);
 hipError_t launch_transfer_t(float2* Ht, int m, int n, double dist, double wavelength, double pixel, hipStream_t s);
 hipError_t launch_sqrt_y(const float* y, float* sy, float2* syc, long long total, hipStream_t s);

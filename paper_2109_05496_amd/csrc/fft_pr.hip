@@ -426,6 +426,77 @@ __global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_kernel(FftA
   }
 }
 
+// Round trip along the columns of an [N][W] image (the transposed spectrum
+// layout: N = n, W = m), for the gradient of Eq. (27): the inverse DFT of every
+// column (which completes A_d x, the m-direction having been inverted by the
+// previous pass), the residual bracket (A x / |A x|)(|A x| - sqrt(y)) in the
+// spatial domain (with float64 loss partials), and the forward DFT of that
+// column again, stored back in the same [N][W] layout - no transpose, and the
+// residual never goes to memory. Column c of the image is row c of the
+// natural-layout image, so sqrt(y) is read at c * N + k. Columns are staged
+// through LDS for row-contiguous loads and stores, as in fft_col_kernel.
+template <int N>
+__global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_roundtrip_kernel(FftArgs a) {
+  constexpr int TPL = N / 16;
+  constexpr int CB = col_block<N>();
+  constexpr int NT = CB * TPL;
+  constexpr int LS = N + N / 16 + 1;
+  __shared__ float2 s[CB * LS];
+  __shared__ double red[(NT + 63) / 64];
+  const long long W = a.lines;
+  const int cl = threadIdx.x / TPL;
+  const long long col = (long long)blockIdx.x * CB + cl;
+  const bool live = col < W;
+  float2* sl = s + cl * LS;
+  const int img = blockIdx.y;
+  const float2* in = a.in + (long long)img * a.in_stride;
+  for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+    const int row = idx / CB, c = idx - (idx / CB) * CB;
+    const long long gc = (long long)blockIdx.x * CB + c;
+    s[c * LS + pidx(row)] = gc < W ? in[(long long)row * W + gc] : make_float2(0.0f, 0.0f);
+  }
+  __syncthreads();
+  float2 o[16];
+  int pos[16];
+  line_fft<N, 1, true>(a, img, col, live, sl, o, pos);
+  double loss = 0.0;
+  const float* sy = a.sy + (long long)img * a.sy_stride + (live ? col : 0) * N;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float2 v = make_float2(o[r].x * a.scale, o[r].y * a.scale);
+    const float am = sqrtf(v.x * v.x + v.y * v.y);
+    const float res = am - (live ? sy[pos[r]] : 0.0f);
+    float2 ph = make_float2(1.0f, 0.0f);
+    if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
+    o[r] = make_float2(ph.x * res, ph.y * res);
+    if (live) loss += 0.5 * (double)res * (double)res;
+  }
+  __syncthreads();  // every thread's last inverse pass has read its line
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = o[r];
+  __syncthreads();
+  line_fft<N, -1, true>(a, img, col, live, sl, o, pos);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = o[r];
+  __syncthreads();
+  float2* out = a.out + (long long)img * a.img_stride;
+  for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+    const int row = idx / CB, c = idx - (idx / CB) * CB;
+    const long long gc = (long long)blockIdx.x * CB + c;
+    if (gc < W) out[(long long)row * W + gc] = s[c * LS + pidx(row)];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = loss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (NT + 63) / 64; ++w) t += red[w];
+    a.partial[(long long)img * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 // out[c][r] = in[r][c] for an R x C complex array per image, 64 x 64 tiles.
 __global__ __launch_bounds__(kThreads) void transpose_kernel(const float2* __restrict__ in, float2* __restrict__ out,
                                                               int R, int C, long long stride) {
@@ -654,6 +725,23 @@ hipError_t launch_fft_second(FftArgs a, int N, long long W, int dir, int batch, 
   if (a.pre != kPreNone) return hipErrorInvalidValue;
   a.lines = W;
   return dir < 0 ? launch_col_dir<-1>(a, N, batch, s) : launch_col_dir<1>(a, N, batch, s);
+}
+
+hipError_t launch_fft_roundtrip(FftArgs a, int N, long long W, int batch, hipStream_t s) {
+  a.lines = W;
+#define CTV_RTK(NN)                                                                            \
+  case NN: {                                                                                   \
+    constexpr int cb = col_block<NN>();                                                        \
+    const dim3 grid((unsigned)((W + cb - 1) / cb), (unsigned)batch);                           \
+    hipLaunchKernelGGL((fft_col_roundtrip_kernel<NN>), grid, dim3(cb * (NN / 16)), 0, s, a);   \
+    break;                                                                                     \
+  }
+  switch (N) {
+    CTV_RTK(32) CTV_RTK(64) CTV_RTK(128) CTV_RTK(256) CTV_RTK(512) CTV_RTK(1024) CTV_RTK(2048) CTV_RTK(4096)
+    default: return hipErrorInvalidValue;
+  }
+#undef CTV_RTK
+  return hipGetLastError();
 }
 
 hipError_t launch_transpose(const float2* in, float2* out, int R, int C, int batch, hipStream_t s) {

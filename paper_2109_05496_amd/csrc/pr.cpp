@@ -211,16 +211,35 @@ ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, 
   a.H = c.Ht(0);
   a.H_stride = c.px;
   CTV_TRY(launch_fft_lines(a, c.m, c.n, 1, c.D, c.s), "ifft (columns)");
-  FftArgs r = line_args(t1, t2, c.at(c.L.tw_n), c.px);
-  r.post = kPostResidual;
-  r.scale = inv;
-  r.sy = c.sy(0);
-  r.sy_stride = c.px;
-  r.partial = part;
-  CTV_TRY(launch_fft_second(r, c.n, c.m, 1, c.D, t2, c.s), "ifft (rows, residual)");
-  // acc = sum_d conj(H_d) FFT2(residual_d)
-  st = accumulate_spectra(c, t2, acc);
-  if (st) return st;
+  if (c.n >= 32) {
+    // along n: inverse, residual, forward again in one pass (t1 -> t2, [n][m]);
+    // then the forward pass along m with acc = sum_d conj(H_d) (.) over the distances
+    FftArgs r = line_args(t1, t2, c.at(c.L.tw_n), c.px);
+    r.scale = inv;
+    r.sy = c.sy(0);
+    r.sy_stride = c.px;
+    r.partial = part;
+    CTV_TRY(launch_fft_roundtrip(r, c.n, c.m, c.D, c.s), "residual round trip");
+    FftArgs q = line_args(t2, nullptr, c.at(c.L.tw_m), c.px);
+    q.post = kPostAccumulateAll;
+    q.H = c.Ht(0);
+    q.H_stride = c.px;
+    q.acc = acc;
+    q.accumulate = 0;
+    q.n_acc = c.D;
+    CTV_TRY(launch_fft_lines(q, c.m, c.n, -1, 1, c.s), "fft (columns, accumulate)");
+  } else {
+    FftArgs r = line_args(t1, t2, c.at(c.L.tw_n), c.px);
+    r.post = kPostResidual;
+    r.scale = inv;
+    r.sy = c.sy(0);
+    r.sy_stride = c.px;
+    r.partial = part;
+    CTV_TRY(launch_fft_second(r, c.n, c.m, 1, c.D, t2, c.s), "ifft (rows, residual)");
+    // acc = sum_d conj(H_d) FFT2(residual_d)
+    st = accumulate_spectra(c, t2, acc);
+    if (st) return st;
+  }
   FftArgs g = epilogue(post_step ? kPostStep : kPostStore, inv);
   g.z = z;
   g.gamma = gamma;
