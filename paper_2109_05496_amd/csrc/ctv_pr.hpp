@@ -52,6 +52,10 @@ int fft_second_blocks(int N, long long W);
 // fft_second_blocks(N, W) blocks per image), forward DFT back; out keeps the
 // [N][W] layout.
 hipError_t launch_fft_roundtrip(FftArgs a, int N, long long W, int batch, hipStream_t s);
+// Along the N-long lines (N >= 32) of the a.n_acc images a.in (stride
+// a.in_stride): out = IDFT(sum_img conj(H_img) (.) a.scale * DFT(line of img)),
+// unscaled, one [lines][N] image (H, H_stride as for kPostAccumulateAll).
+hipError_t launch_fft_acc_inverse(FftArgs a, int N, long long lines, hipStream_t s);
 hipError_t launch_twiddles(float2* tw, int N, hipStream_t s);
 hipError_t launch_transfer_t(float2* Ht, int m, int n, double dist, double wavelength, double pixel, hipStream_t s);
 hipError_t launch_sqrt_y(const float* y, float* sy, float2* syc, long long total, hipStream_t s);

@@ -19,6 +19,7 @@
 // conj(H_d) * (.), or take the gradient step z - gamma * (.).
 // Twiddles and transfer functions are built on the device in float64 (the
 // propagation phase 2 pi d / lambda_s reaches ~3e4 rad) and stored as float2.
+#include <climits>
 #include <hip/hip_runtime.h>
 
 #include "ctv_device.hpp"
@@ -129,44 +130,75 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
-// The last-pass epilogue applied to the element at linear index p of image `img`.
-__device__ __forceinline__ void post_op(const FftArgs& a, int img, long long p, float2 v, double& loss) {
-  v.x *= a.scale;
-  v.y *= a.scale;
-  const long long base = (long long)img * a.img_stride;
+// The last-pass epilogue for CNT elements of image `img` at linear indices
+// lbase + pos[r]. The epilogue kind is tested once for the whole block, so the
+// side loads (sqrt(y) or z) of all CNT elements are in flight together instead
+// of each waiting in a branch of its own.
+template <int CNT>
+__device__ __forceinline__ void post_block(const FftArgs& a, int img, long long lbase, const int (&pos)[16],
+                                           float2 (&v)[16], double& loss) {
+#pragma unroll
+  for (int r = 0; r < CNT; ++r) v[r] = make_float2(v[r].x * a.scale, v[r].y * a.scale);
+  float2* out = a.out + (long long)img * a.img_stride + lbase;
   if (a.post == kPostStore) {
-    a.out[base + p] = v;
-  } else if (a.post == kPostResidual) {
-    // (A x / |A x|)(|A x| - sqrt(y)): the bracket of Eq. (27), unit phasor where A x = 0
-    const float am = sqrtf(v.x * v.x + v.y * v.y);
-    const float r = am - a.sy[(long long)img * a.sy_stride + p];
-    float2 ph = make_float2(1.0f, 0.0f);
-    if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
-    a.out[base + p] = make_float2(ph.x * r, ph.y * r);
-    loss += 0.5 * (double)r * (double)r;
-  } else if (a.post == kPostStep) {
-    const float2 z = a.z[p];
-    a.out[base + p] = make_float2(fmaf(-a.gamma, v.x, z.x), fmaf(-a.gamma, v.y, z.y));
-  } else if (a.post == kPostReplace) {
-    // keep the phase, impose the measured modulus (unit phasor where the field is 0)
-    const float am = sqrtf(v.x * v.x + v.y * v.y);
-    const float sy = a.sy[(long long)img * a.sy_stride + p];
-    float2 ph = make_float2(1.0f, 0.0f);
-    if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
-    a.out[base + p] = make_float2(ph.x * sy, ph.y * sy);
-  } else {  // kPostProjC: v / max{1, |v|} (Eq. 26)
-    if (a.constr) {
-      const float am = sqrtf(v.x * v.x + v.y * v.y);
-      if (am > 1.0f) v = make_float2(v.x / am, v.y / am);
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) out[pos[r]] = v[r];
+  } else if (a.post == kPostResidual || a.post == kPostReplace) {
+    // residual: (A x / |A x|)(|A x| - sqrt(y)), the bracket of Eq. (27);
+    // replace: (A x / |A x|) sqrt(y), the measured modulus with the phase kept;
+    // both with the unit phasor where A x = 0
+    const float* sy = a.sy + (long long)img * a.sy_stride + lbase;
+    float y[16];
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) y[r] = sy[pos[r]];
+    const bool res = a.post == kPostResidual;
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) {
+      const float am = sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
+      const float mag = res ? am - y[r] : y[r];
+      float2 ph = make_float2(1.0f, 0.0f);
+      if (am > 0.0f) ph = make_float2(v[r].x / am, v[r].y / am);
+      out[pos[r]] = make_float2(ph.x * mag, ph.y * mag);
+      if (res) loss += 0.5 * (double)mag * (double)mag;
     }
-    a.out[base + p] = v;
+  } else if (a.post == kPostStep) {
+    const float2* z = a.z + lbase;
+    float2 zz[16];
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) zz[r] = z[pos[r]];
+#pragma unroll
+    for (int r = 0; r < CNT; ++r)
+      out[pos[r]] = make_float2(fmaf(-a.gamma, v[r].x, zz[r].x), fmaf(-a.gamma, v[r].y, zz[r].y));
+  } else {  // kPostProjC: v / max{1, |v|} (Eq. 26)
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) {
+      float2 w = v[r];
+      if (a.constr) {
+        const float am = sqrtf(w.x * w.x + w.y * w.y);
+        if (am > 1.0f) w = make_float2(w.x / am, w.y / am);
+      }
+      out[pos[r]] = w;
+    }
   }
 }
 
-__device__ __forceinline__ float2 pre_op(const FftArgs& a, int img, long long p, float2 v) {
-  if (a.pre == kPreNone) return v;
-  const float2 h = a.H[(long long)img * a.H_stride + p];
-  return cmul(v, a.pre == kPreMulH ? h : conjf2(h));
+// Loads CNT elements of image `img` at p0 + r * STRIDE into v, multiplied by H
+// or conj(H) at the same positions when a.pre asks for it (all loads issued
+// before the first use).
+template <int CNT, int STRIDE>
+__device__ __forceinline__ void load_pre(const FftArgs& a, int img, long long p0, float2 (&v)[16]) {
+  const float2* in = a.in + (long long)img * a.in_stride + p0;
+#pragma unroll
+  for (int r = 0; r < CNT; ++r) v[r] = in[r * STRIDE];
+  if (a.pre != kPreNone) {
+    const float2* H = a.H + (long long)img * a.H_stride + p0;
+    float2 h[16];
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) h[r] = H[r * STRIDE];
+    const bool cj = a.pre != kPreMulH;
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) v[r] = cmul(v[r], cj ? conjf2(h[r]) : h[r]);
+  }
 }
 
 template <int DIR>
@@ -195,34 +227,23 @@ __device__ __forceinline__ void pass_lds(const float2* L, float2 (&v)[16], int j
   dft<R, DIR>(v);
 }
 
-// The FFT of one line (image `img`, line `line`) up to the last pass, whose 16
-// outputs per thread are returned in o[] with their positions within the line.
-// FROM_LDS: the line is already staged in sl (natural order, pidx positions)
-// and the first pass reads it from there instead of global memory.
-template <int N, int DIR, bool FROM_LDS = false>
-__device__ __forceinline__ void line_fft(const FftArgs& a, int img, long long line, bool live, float2* sl,
-                                         float2 (&o)[16], int (&pos)[16]) {
+// The FFT of one line from the first radix-16 pass on, the thread's 16 inputs
+// (line positions lt + r * N/16) already in v; the 16 outputs of the last
+// pass are returned in o[] with their positions within the line in pos[].
+// OPAQUE_LANE: take the lane index through an empty asm, so that a second
+// transform in the same kernel recomputes its LDS and twiddle offsets instead
+// of keeping the first one's alive in registers.
+template <int N, int DIR, bool OPAQUE_LANE = false>
+__device__ __forceinline__ void line_fft_regs(const FftArgs& a, float2* sl, float2 (&v)[16], float2 (&o)[16],
+                                              int (&pos)[16]) {
   constexpr int TPL = N / 16;                  // threads per line
   constexpr int L = (N == 32) ? 5 : (N == 64) ? 6 : (N == 128) ? 7 : (N == 256) ? 8 : (N == 512) ? 9
                   : (N == 1024) ? 10 : (N == 2048) ? 11 : 12;
   constexpr int P16 = L / 4;                   // radix-16 passes
   constexpr int RR = 1 << (L % 4);             // remainder radix (1 = none)
   constexpr int NPASS = P16 + (RR > 1 ? 1 : 0);  // >= 2 for N >= 32
-  const int lt = threadIdx.x % TPL;
-  const long long rowbase = line * N;
-  const float2* in = a.in + (long long)img * a.in_stride;
-  float2 v[16];
-  // pass 1: radix 16 straight from global memory (Ns = 1, no twiddles)
-  if (FROM_LDS) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = sl[pidx(lt + r * TPL)];
-  } else if (live) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = pre_op(a, img, rowbase + lt + r * TPL, in[rowbase + lt + r * TPL]);
-  } else {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
-  }
+  int lt = threadIdx.x % TPL;
+  if (OPAQUE_LANE) asm volatile("" : "+v"(lt));
   dft<16, DIR>(v);
   int Ns = 16;
   __syncthreads();  // the previous use of this LDS line (an earlier image) is finished
@@ -270,6 +291,30 @@ __device__ __forceinline__ void line_fft(const FftArgs& a, int img, long long li
   }
 }
 
+// The FFT of one line (image `img`, line `line`) up to the last pass, whose 16
+// outputs per thread are returned in o[] with their positions within the line.
+// FROM_LDS: the line is already staged in sl (natural order, pidx positions)
+// and the first pass reads it from there instead of global memory.
+template <int N, int DIR, bool FROM_LDS = false>
+__device__ __forceinline__ void line_fft(const FftArgs& a, int img, long long line, bool live, float2* sl,
+                                         float2 (&o)[16], int (&pos)[16]) {
+  constexpr int TPL = N / 16;                  // threads per line
+  const int lt = threadIdx.x % TPL;
+  const long long rowbase = line * N;
+  float2 v[16];
+  // pass 1: radix 16 straight from global memory (Ns = 1, no twiddles)
+  if (FROM_LDS) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = sl[pidx(lt + r * TPL)];
+  } else if (live) {
+    load_pre<16, TPL>(a, img, rowbase + lt, v);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
+  }
+  line_fft_regs<N, DIR>(a, sl, v, o, pos);
+}
+
 template <int N, int DIR, bool ACCALL>
 __global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
   constexpr int TPL = N / 16;
@@ -310,13 +355,80 @@ __global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
   const int img = blockIdx.y;
   line_fft<N, DIR>(a, img, line, live, sl, o, pos);
   double loss = 0.0;
-  if (live) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) post_op(a, img, line * N + pos[r], o[r], loss);
-  }
+  if (live) post_block<16>(a, img, line * N, pos, o, loss);
   if (a.post == kPostResidual) {
     const double tot = block_sum(loss, red);
     if (threadIdx.x == 0) a.partial[(long long)img * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+// Along the lines of [lines][N] images (the m-direction of the transposed
+// spectrum layout, N >= 32): the forward DFT of a line of each of the n_acc
+// images, scaled by a.scale and multiplied by conj(H_img) at the same
+// frequencies, summed over the images (the sum over distances of Eq. (27)),
+// then the inverse DFT of that sum along the same line, stored unscaled in
+// a.out ([lines][N]) - the accumulate pass and the first inverse pass of the
+// gradient in one. G groups of a block transform different images of the same
+// line side by side (group g takes images g, g + G, ...), so a line's images
+// are in flight together; the group partials are then added in group order
+// (for n_acc <= G that is the sequential order over the images) and every
+// group runs the inverse (all take part in its barriers), group 0 storing it.
+template <int N>
+constexpr int acc_groups() { return (kThreads / (N / 16)) < 4 ? (kThreads / (N / 16)) : 4; }
+template <int N>
+constexpr int acc_lines_per_block() { return (kThreads / (N / 16)) / acc_groups<N>(); }
+
+// ONE: n_acc <= G, every group transforms at most one image (no running sum).
+template <int N, bool ONE>
+__global__ __launch_bounds__(kThreads) void fft_acc_inverse_kernel(FftArgs a) {
+  constexpr int TPL = N / 16;
+  constexpr int SLOTS = kThreads / TPL;        // line slots per block
+  constexpr int G = acc_groups<N>();           // image groups per line
+  constexpr int LPB = acc_lines_per_block<N>();
+  constexpr int LS = N + N / 16;
+  __shared__ float2 s[SLOTS * LS];
+  const int slot = threadIdx.x / TPL;
+  const int g = slot % G, li = slot / G;
+  const int lt = threadIdx.x % TPL;
+  const long long line = (long long)blockIdx.x * LPB + li;
+  const bool live = line < a.lines;
+  float2* sl = s + slot * LS;
+  float2 sum[16], o[16];
+  int pos[16];
+  const int rounds = ONE ? 1 : (a.n_acc + G - 1) / G;  // the same for every group: barriers match
+  for (int it = 0; it < rounds; ++it) {
+    const int img = g + it * G;
+    const bool act = live && img < a.n_acc;
+    line_fft<N, -1>(a, act ? img : 0, line, act, sl, o, pos);
+    float2 h[16];
+    const float2* H = a.H + (long long)(act ? img : 0) * a.H_stride + line * N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) h[r] = act ? H[pos[r]] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float2 t = cmul(conjf2(h[r]), make_float2(o[r].x * a.scale, o[r].y * a.scale));
+      sum[r] = it == 0 ? t : cadd(sum[r], t);
+    }
+  }
+  __syncthreads();  // every group's last pass has read its line
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = sum[r];
+  __syncthreads();
+  const float2* s0 = s + (li * G) * LS;
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int p = pidx(lt + r * TPL);
+    float2 t = s0[p];
+#pragma unroll
+    for (int gg = 1; gg < G; ++gg) t = cadd(t, s0[gg * LS + p]);
+    v[r] = t;
+  }
+  line_fft_regs<N, 1, true>(a, sl, v, o, pos);
+  if (live && g == 0) {
+    float2* out = a.out + line * N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[pos[r]] = o[r];
   }
 }
 
@@ -332,12 +444,10 @@ __global__ __launch_bounds__(kThreads) void fft_small_kernel(FftArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) sum[r] = make_float2(0.0f, 0.0f);
     for (int img = 0; img < a.n_acc; ++img) {
-      const float2* in = a.in + (long long)img * a.in_stride;
       float2 v[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
-#pragma unroll
-      for (int r = 0; r < N; ++r) v[r] = pre_op(a, img, line * N + r, in[line * N + r]);
+      load_pre<N, 1>(a, img, line * N, v);
       dft<N, DIR>(v);
 #pragma unroll
       for (int r = 0; r < N; ++r) {
@@ -354,15 +464,15 @@ __global__ __launch_bounds__(kThreads) void fft_small_kernel(FftArgs a) {
   }
   const int img = blockIdx.y;
   if (line < a.lines) {
-    const float2* in = a.in + (long long)img * a.in_stride;
     float2 v[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = pre_op(a, img, line * N + r, in[line * N + r]);
+    load_pre<N, 1>(a, img, line * N, v);
     dft<N, DIR>(v);
+    int pos[16];
 #pragma unroll
-    for (int r = 0; r < N; ++r) post_op(a, img, line * N + r, v[r], loss);
+    for (int r = 0; r < 16; ++r) pos[r] = r;
+    post_block<N>(a, img, line * N, pos, v, loss);
   }
   if (a.post == kPostResidual) {
     const double tot = block_sum(loss, red);
@@ -382,6 +492,50 @@ __global__ __launch_bounds__(kThreads) void fft_small_kernel(FftArgs a) {
 template <int N>
 constexpr int col_block() { return (512 / (N / 16)) < 8 ? (512 / (N / 16)) : 8; }
 
+// Stage CB columns of an [N][W] image into LDS (column c at s + c * LS, pidx
+// positions) with row-contiguous loads: the 16 loads of a thread are all issued
+// before the first LDS write, so they are in flight together (N * CB = 16 NT).
+// A thread's column is the same for all 16 (NT is a multiple of CB) and its
+// rows are row0 + k * TPL; past the last column it loads column W - 1 and
+// stages zeros, so that no load sits in a branch of its own (which would make
+// each wait for the previous one). Offsets within an image are 32-bit (the
+// launchers check N * W < 2^31), one register per address.
+template <int N, int CB, int NT, int LS>
+__device__ __forceinline__ void stage_columns(const float2* __restrict__ in, int W, float2* s) {
+  static_assert(N * CB == 16 * NT && NT % CB == 0, "16 elements per thread, one column per thread");
+  constexpr int RSTEP = NT / CB;  // rows between a thread's consecutive elements
+  const int c = threadIdx.x % CB, row0 = threadIdx.x / CB;
+  const int gc = blockIdx.x * CB + c;
+  const bool in_range = gc < W;
+  const int base = row0 * W + (in_range ? gc : W - 1);
+  float2 v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = in[base + k * RSTEP * W];
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (!in_range) v[k] = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s[c * LS + pidx(row0 + k * RSTEP)] = v[k];
+  __syncthreads();
+}
+
+// The inverse of stage_columns: CB staged columns back to an [N][W] image
+// with row-contiguous stores (columns past W are not written).
+template <int N, int CB, int NT, int LS>
+__device__ __forceinline__ void unstage_columns(const float2* s, int W, float2* __restrict__ out) {
+  constexpr int RSTEP = NT / CB;
+  const int c = threadIdx.x % CB, row0 = threadIdx.x / CB;
+  const int gc = blockIdx.x * CB + c;
+  float2 v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = s[c * LS + pidx(row0 + k * RSTEP)];
+  if (gc < W) {
+    const int base = row0 * W + gc;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) out[base + k * RSTEP * W] = v[k];
+  }
+}
+
 template <int N, int DIR>
 __global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_kernel(FftArgs a) {
   constexpr int TPL = N / 16;
@@ -396,23 +550,12 @@ __global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_kernel(FftA
   const bool live = col < W;
   float2* sl = s + cl * LS;
   const int img = blockIdx.y;
-  {
-    const float2* in = a.in + (long long)img * a.in_stride;
-    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
-      const int row = idx / CB, c = idx - (idx / CB) * CB;
-      const long long gc = (long long)blockIdx.x * CB + c;
-      s[c * LS + pidx(row)] = gc < W ? in[(long long)row * W + gc] : make_float2(0.0f, 0.0f);
-    }
-    __syncthreads();
-  }
+  stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, s);
   float2 o[16];
   int pos[16];
   line_fft<N, DIR, true>(a, img, col, live, sl, o, pos);
   double loss = 0.0;
-  if (live) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) post_op(a, img, col * N + pos[r], o[r], loss);
-  }
+  if (live) post_block<16>(a, img, col * N, pos, o, loss);
   if (a.post == kPostResidual) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
@@ -435,8 +578,10 @@ __global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_kernel(FftA
 // residual never goes to memory. Column c of the image is row c of the
 // natural-layout image, so sqrt(y) is read at c * N + k. Columns are staged
 // through LDS for row-contiguous loads and stores, as in fft_col_kernel.
+// Two blocks share a CU (the LDS fits two), so at most 128 VGPRs per lane.
 template <int N>
-__global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_roundtrip_kernel(FftArgs a) {
+__global__ __launch_bounds__(col_block<N>() * (N / 16)) __attribute__((amdgpu_waves_per_eu(4)))
+void fft_col_roundtrip_kernel(FftArgs a) {
   constexpr int TPL = N / 16;
   constexpr int CB = col_block<N>();
   constexpr int NT = CB * TPL;
@@ -449,43 +594,40 @@ __global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_roundtrip_k
   const bool live = col < W;
   float2* sl = s + cl * LS;
   const int img = blockIdx.y;
-  const float2* in = a.in + (long long)img * a.in_stride;
-  for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
-    const int row = idx / CB, c = idx - (idx / CB) * CB;
-    const long long gc = (long long)blockIdx.x * CB + c;
-    s[c * LS + pidx(row)] = gc < W ? in[(long long)row * W + gc] : make_float2(0.0f, 0.0f);
-  }
-  __syncthreads();
+  stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, s);
   float2 o[16];
   int pos[16];
   line_fft<N, 1, true>(a, img, col, live, sl, o, pos);
-  double loss = 0.0;
-  const float* sy = a.sy + (long long)img * a.sy_stride + (live ? col : 0) * N;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const float2 v = make_float2(o[r].x * a.scale, o[r].y * a.scale);
-    const float am = sqrtf(v.x * v.x + v.y * v.y);
-    const float res = am - (live ? sy[pos[r]] : 0.0f);
-    float2 ph = make_float2(1.0f, 0.0f);
-    if (am > 0.0f) ph = make_float2(v.x / am, v.y / am);
-    o[r] = make_float2(ph.x * res, ph.y * res);
-    if (live) loss += 0.5 * (double)res * (double)res;
-  }
   __syncthreads();  // every thread's last inverse pass has read its line
 #pragma unroll
   for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = o[r];
   __syncthreads();
-  line_fft<N, -1, true>(a, img, col, live, sl, o, pos);
+  // the residual at the positions lt + r * TPL, which are the inputs of this
+  // thread's first forward pass: the forward transform starts from registers
+  const int lt = threadIdx.x % TPL;
+  const float* sy = a.sy + (long long)img * a.sy_stride + (live ? col : 0) * N + lt;
+  float y[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) y[r] = sy[r * TPL];
+  float2 v[16];
+  double loss = 0.0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const float2 w = sl[pidx(lt + r * TPL)];
+    const float2 u = make_float2(w.x * a.scale, w.y * a.scale);
+    const float am = sqrtf(u.x * u.x + u.y * u.y);
+    const float res = am - (live ? y[r] : 0.0f);
+    float2 ph = make_float2(1.0f, 0.0f);
+    if (am > 0.0f) ph = make_float2(u.x / am, u.y / am);
+    v[r] = make_float2(ph.x * res, ph.y * res);
+    if (live) loss += 0.5 * (double)res * (double)res;
+  }
+  line_fft_regs<N, -1, true>(a, sl, v, o, pos);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = o[r];
   __syncthreads();
-  float2* out = a.out + (long long)img * a.img_stride;
-  for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
-    const int row = idx / CB, c = idx - (idx / CB) * CB;
-    const long long gc = (long long)blockIdx.x * CB + c;
-    if (gc < W) out[(long long)row * W + gc] = s[c * LS + pidx(row)];
-  }
+  unstage_columns<N, CB, NT, LS>(s, (int)W, a.out + (long long)img * a.img_stride);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = loss;
@@ -723,11 +865,13 @@ hipError_t launch_fft_second(FftArgs a, int N, long long W, int dir, int batch, 
     return launch_fft_lines(a, N, W, dir, batch, s);
   }
   if (a.pre != kPreNone) return hipErrorInvalidValue;
+  if ((long long)N * W > INT_MAX) return hipErrorInvalidValue;  // 32-bit offsets within an image
   a.lines = W;
   return dir < 0 ? launch_col_dir<-1>(a, N, batch, s) : launch_col_dir<1>(a, N, batch, s);
 }
 
 hipError_t launch_fft_roundtrip(FftArgs a, int N, long long W, int batch, hipStream_t s) {
+  if ((long long)N * W > INT_MAX) return hipErrorInvalidValue;  // 32-bit offsets within an image
   a.lines = W;
 #define CTV_RTK(NN)                                                                            \
   case NN: {                                                                                   \
@@ -741,6 +885,26 @@ hipError_t launch_fft_roundtrip(FftArgs a, int N, long long W, int batch, hipStr
     default: return hipErrorInvalidValue;
   }
 #undef CTV_RTK
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_acc_inverse(FftArgs a, int N, long long lines, hipStream_t s) {
+  a.lines = lines;
+#define CTV_AIK(NN)                                                                     \
+  case NN: {                                                                            \
+    constexpr int lpb = acc_lines_per_block<NN>();                                      \
+    const dim3 grid((unsigned)((lines + lpb - 1) / lpb));                               \
+    if (a.n_acc <= acc_groups<NN>())                                                    \
+      hipLaunchKernelGGL((fft_acc_inverse_kernel<NN, true>), grid, dim3(kThreads), 0, s, a); \
+    else                                                                                \
+      hipLaunchKernelGGL((fft_acc_inverse_kernel<NN, false>), grid, dim3(kThreads), 0, s, a); \
+    break;                                                                              \
+  }
+  switch (N) {
+    CTV_AIK(32) CTV_AIK(64) CTV_AIK(128) CTV_AIK(256) CTV_AIK(512) CTV_AIK(1024) CTV_AIK(2048) CTV_AIK(4096)
+    default: return hipErrorInvalidValue;
+  }
+#undef CTV_AIK
   return hipGetLastError();
 }
 

@@ -220,6 +220,25 @@ ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, 
     r.sy_stride = c.px;
     r.partial = part;
     CTV_TRY(launch_fft_roundtrip(r, c.n, c.m, c.D, c.s), "residual round trip");
+    if (c.m >= 32) {
+      // along m: forward, sum_d conj(H_d) (.) over the distances, inverse of the
+      // sum (t2 -> t1, [n][m]); then the inverse along n with the epilogue
+      FftArgs q = line_args(t2, t1, c.at(c.L.tw_m), c.px);
+      q.H = c.Ht(0);
+      q.H_stride = c.px;
+      q.n_acc = c.D;
+      CTV_TRY(launch_fft_acc_inverse(q, c.m, c.n, c.s), "fft (columns, accumulate, inverse)");
+      FftArgs g = epilogue(post_step ? kPostStep : kPostStore, inv);
+      g.z = z;
+      g.gamma = gamma;
+      g.in = t1;
+      g.out = out;
+      g.tw = c.at(c.L.tw_n);
+      g.in_stride = g.img_stride = c.px;
+      CTV_TRY(launch_fft_second(g, c.n, c.m, 1, 1, t2, c.s), "ifft (rows)");
+      if (loss) CTV_TRY(launch_loss_final(part, c.D * rb, loss, c.s), "loss");
+      return CTV_OK;
+    }
     FftArgs q = line_args(t2, nullptr, c.at(c.L.tw_m), c.px);
     q.post = kPostAccumulateAll;
     q.H = c.Ht(0);

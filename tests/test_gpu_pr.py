@@ -233,6 +233,29 @@ def test_line_search_and_warm_start_config5():
     assert float(x.abs().max()) <= 1 + 1e-6
 
 
+@pytest.mark.parametrize("m,n,D", [(64, 64, 6), (32, 32, 9), (16, 64, 3), (64, 16, 2), (128, 64, 5)])
+def test_gradient_distance_counts_and_short_lines(m, n, D):
+    """The gradient's last forward pass sums conj(H_d) over the distances and
+    inverts the sum in one launch, up to four distances side by side: more
+    than four distances (a running sum per group), and lines shorter than 32
+    (the separate accumulate pass) against the oracle."""
+    big = synth.config5_object(seed=11, size=max(m, n), n_shapes=10, sigma_px=2.0)
+    truth = big[:m, :n]
+    dists = [P5["distances"][d % 4] * (1.0 + 0.25 * (d // 4)) for d in range(D)]
+    Hs = [opr.transfer(m, n, d, P5["wavelength"], P5["pixel"]) for d in dists]
+    rng = np.random.default_rng(11)
+    y = np.stack([synth.poisson_measure(np.abs(opr.A(truth, H)) ** 2, P5["photons"], rng) for H in Hs])
+    x = (truth * np.exp(0.2j) + 0.05).astype(np.complex64)
+    g, loss = ctv().pr_gradient(dev(x), dev(y), dists, P5["wavelength"], P5["pixel"])
+    sy = [np.sqrt(np.maximum(yy.astype(np.float64), 0)) for yy in y]
+    gref = opr.grad_F(x.astype(np.complex128), sy, Hs)
+    print("gradient", m, n, D, "rel-L2", rel(g.cpu().numpy(), gref), "elementwise", elem(g.cpu().numpy(), gref))
+    assert rel(g.cpu().numpy(), gref) <= 1e-5
+    assert elem(g.cpu().numpy(), gref) <= ELEM_TOL, elem(g.cpu().numpy(), gref)
+    lref = opr.data_term(x.astype(np.complex128), sy, Hs)
+    assert abs(float(loss.cpu()[0]) - lref) <= 1e-5 * lref
+
+
 @pytest.mark.parametrize("m,n", [(64, 128), (128, 32)])
 def test_non_square_problem_matches_oracle(m, n):
     """m != n exercises the transposed spectrum layout ([n][m]) and the
