@@ -492,8 +492,8 @@ __global__ __launch_bounds__(kThreads) void fft_small_kernel(FftArgs a) {
 template <int N>
 constexpr int col_block() { return (512 / (N / 16)) < 8 ? (512 / (N / 16)) : 8; }
 
-// Stage CB columns of an [N][W] image into LDS (column c at s + c * LS, pidx
-// positions) with row-contiguous loads: the 16 loads of a thread are all issued
+// Stage the CB columns of group grp of an [N][W] image into LDS (column c at
+// s + c * LS, pidx positions) with row-contiguous loads: the 16 loads of a thread are all issued
 // before the first LDS write, so they are in flight together (N * CB = 16 NT).
 // A thread's column is the same for all 16 (NT is a multiple of CB) and its
 // rows are row0 + k * TPL; past the last column it loads column W - 1 and
@@ -501,11 +501,11 @@ constexpr int col_block() { return (512 / (N / 16)) < 8 ? (512 / (N / 16)) : 8; 
 // each wait for the previous one). Offsets within an image are 32-bit (the
 // launchers check N * W < 2^31), one register per address.
 template <int N, int CB, int NT, int LS>
-__device__ __forceinline__ void stage_columns(const float2* __restrict__ in, int W, float2* s) {
+__device__ __forceinline__ void stage_columns(const float2* __restrict__ in, int W, int grp, float2* s) {
   static_assert(N * CB == 16 * NT && NT % CB == 0, "16 elements per thread, one column per thread");
   constexpr int RSTEP = NT / CB;  // rows between a thread's consecutive elements
   const int c = threadIdx.x % CB, row0 = threadIdx.x / CB;
-  const int gc = blockIdx.x * CB + c;
+  const int gc = grp * CB + c;
   const bool in_range = gc < W;
   const int base = row0 * W + (in_range ? gc : W - 1);
   float2 v[16];
@@ -522,10 +522,10 @@ __device__ __forceinline__ void stage_columns(const float2* __restrict__ in, int
 // The inverse of stage_columns: CB staged columns back to an [N][W] image
 // with row-contiguous stores (columns past W are not written).
 template <int N, int CB, int NT, int LS>
-__device__ __forceinline__ void unstage_columns(const float2* s, int W, float2* __restrict__ out) {
+__device__ __forceinline__ void unstage_columns(const float2* s, int W, int grp, float2* __restrict__ out) {
   constexpr int RSTEP = NT / CB;
   const int c = threadIdx.x % CB, row0 = threadIdx.x / CB;
-  const int gc = blockIdx.x * CB + c;
+  const int gc = grp * CB + c;
   float2 v[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = s[c * LS + pidx(row0 + k * RSTEP)];
@@ -546,11 +546,12 @@ __global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_kernel(FftA
   __shared__ double red[(NT + 63) / 64];
   const long long W = a.lines;
   const int cl = threadIdx.x / TPL;
-  const long long col = (long long)blockIdx.x * CB + cl;
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring column groups share an L2
+  const long long col = (long long)grp * CB + cl;
   const bool live = col < W;
   float2* sl = s + cl * LS;
   const int img = blockIdx.y;
-  stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, s);
+  stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, grp, s);
   float2 o[16];
   int pos[16];
   line_fft<N, DIR, true>(a, img, col, live, sl, o, pos);
@@ -590,11 +591,12 @@ void fft_col_roundtrip_kernel(FftArgs a) {
   __shared__ double red[(NT + 63) / 64];
   const long long W = a.lines;
   const int cl = threadIdx.x / TPL;
-  const long long col = (long long)blockIdx.x * CB + cl;
+  const int grp = xcd_remap(blockIdx.x, gridDim.x);  // neighbouring column groups share an L2
+  const long long col = (long long)grp * CB + cl;
   const bool live = col < W;
   float2* sl = s + cl * LS;
   const int img = blockIdx.y;
-  stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, s);
+  stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, grp, s);
   float2 o[16];
   int pos[16];
   line_fft<N, 1, true>(a, img, col, live, sl, o, pos);
@@ -627,7 +629,7 @@ void fft_col_roundtrip_kernel(FftArgs a) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = o[r];
   __syncthreads();
-  unstage_columns<N, CB, NT, LS>(s, (int)W, a.out + (long long)img * a.img_stride);
+  unstage_columns<N, CB, NT, LS>(s, (int)W, grp, a.out + (long long)img * a.img_stride);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = loss;
