@@ -488,7 +488,9 @@ __global__ __launch_bounds__(kThreads) void fft_small_kernel(FftArgs a) {
 // each column's result is stored as one contiguous line. Same epilogues as the
 // line kernel, indexed in the output layout (no pre-multiply, no
 // accumulate-all). 8 columns per block (two blocks per CU at N = 1024)
-// measured faster than 16 (one block per CU) or 4 (32-byte row segments).
+// measured faster than 16 (one block per CU) or 4 (32-byte row segments) when
+// there are blocks for every CU; a single image of fewer than 2048 columns
+// gives fewer, and then 4 columns per block spread it over twice the CUs.
 template <int N>
 constexpr int col_block() { return (512 / (N / 16)) < 8 ? (512 / (N / 16)) : 8; }
 
@@ -536,10 +538,9 @@ __device__ __forceinline__ void unstage_columns(const float2* s, int W, int grp,
   }
 }
 
-template <int N, int DIR>
-__global__ __launch_bounds__(col_block<N>() * (N / 16)) void fft_col_kernel(FftArgs a) {
+template <int N, int DIR, int CB>
+__global__ __launch_bounds__(CB * (N / 16)) void fft_col_kernel(FftArgs a) {
   constexpr int TPL = N / 16;
-  constexpr int CB = col_block<N>();
   constexpr int NT = CB * TPL;
   constexpr int LS = N + N / 16 + 1;  // padded line; the odd pitch spreads the staging writes over banks
   __shared__ float2 s[CB * LS];
@@ -835,12 +836,21 @@ hipError_t launch_fft_lines(FftArgs a, int N, long long lines, int dir, int batc
 
 template <int DIR>
 static hipError_t launch_col_dir(const FftArgs& a, int N, int batch, hipStream_t s) {
-#define CTV_COLK(NN)                                                                   \
-  case NN: {                                                                           \
-    constexpr int cb = col_block<NN>();                                                \
-    const dim3 grid((unsigned)((a.lines + cb - 1) / cb), (unsigned)batch);             \
-    hipLaunchKernelGGL((fft_col_kernel<NN, DIR>), grid, dim3(cb * (NN / 16)), 0, s, a); \
-    break;                                                                             \
+  // 4 columns per block where 8 would leave CUs idle (not for the residual
+  // epilogue, whose loss partials are counted per 8-column block)
+  const bool narrow = a.post != kPostResidual && (a.lines + 7) / 8 * batch < 256;
+#define CTV_COLK(NN)                                                                        \
+  case NN: {                                                                                \
+    constexpr int cb = col_block<NN>();                                                     \
+    constexpr int cbn = cb == 8 && NN >= 256 ? 4 : cb;                                      \
+    if (narrow && cbn != cb) {                                                              \
+      const dim3 grid((unsigned)((a.lines + cbn - 1) / cbn), (unsigned)batch);             \
+      hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cbn>), grid, dim3(cbn * (NN / 16)), 0, s, a); \
+    } else {                                                                                \
+      const dim3 grid((unsigned)((a.lines + cb - 1) / cb), (unsigned)batch);                \
+      hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cb>), grid, dim3(cb * (NN / 16)), 0, s, a); \
+    }                                                                                       \
+    break;                                                                                  \
   }
   switch (N) {
     CTV_COLK(32) CTV_COLK(64) CTV_COLK(128) CTV_COLK(256) CTV_COLK(512) CTV_COLK(1024) CTV_COLK(2048) CTV_COLK(4096)
