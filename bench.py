@@ -51,6 +51,16 @@ FLOPS_PER_PX_IT = {"1i": 52, "1a": 52, "2i": 52, "2a": 44}
 # the dual step 8, the P_S scale or clip 6 / 8 / 10 / 8, the in-place update 12.
 OPS_PER_PX_IT = {"1i": 41, "1a": 43, "2i": 45, "2a": 43}
 KIND_INDEX = {"1i": 0, "1a": 1, "2i": 2, "2a": 3}
+# Unfused algorithmic bytes of the secondary workloads: the backward per
+# pixel-iteration (recompute 56 + r history 16 + reverse step 120 - rounded
+# to 190), and one phase-retrieval outer iteration per pixel (FGP 20 x 56 +
+# 10 FFT2 x 2 passes x 16 B + H 64 + y 16 + the sum over distances 64 + FISTA
+# 48), of which the FFT side (everything but the FGP prox) is 464 B.
+ADJ_BYTES_PER_PX_IT = 190
+PR_BYTES_PER_PX_OUTER = 1640
+PR_FFT_BYTES_PER_PX_OUTER = 464
+ADJ_PROFILES = ("adjoint_16x512sq_K50_ckpt10_stats.md", "adjoint_16x512sq_K50_ckpt10_pmc.md")
+PR_PROFILES = ("pr_1024sq_D4_100x20_stats.md", "pr_1024sq_D4_100x20_pmc.md")
 PMC_PROFILE = "fgp_batched_kernel_2048sq_masked_4kinds_K200_pmc.md"
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TUNING_TABLE = os.path.join(ROOT, "paper_2109_05496_amd", "tuning", "mi355x.jsonl")
@@ -81,6 +91,9 @@ def parse():
                          "off = the library default")
     ap.add_argument("--tuning-table", default=TUNING_TABLE)
     ap.add_argument("--save-tuning", default=None, help="write the tuning table here at the end")
+    ap.add_argument("--only", choices=("adjoint", "pr"), default=None,
+                    help="run only this secondary measurement, timed part only (for profiling it); prints "
+                         "{\"only\": ..., <entry>: {...}} instead of the result line")
     return ap.parse_args()
 
 
@@ -296,6 +309,48 @@ def bench_batched(ctv, synth, torch, dev, tuner, reps=3):
             "plain_Mpx_it_s": round(px_it / ms_plain / 1e3, 1), "bitwise_equal_to_plain": bool(same)}
 
 
+def profile_figures(names, marker, keep):
+    """Per-kernel figures of a secondary workload from its committed rocprofv3
+    summaries (kernel-trace statistics and PMC counters of `bench.py --only`):
+    launches per unit (the launches of the kernel whose name contains `marker`
+    run once per unit), average duration, measured traffic per launch and its
+    rate, VALU issue utilisation. Kernels whose names contain none of `keep` are
+    left out. None while the kernel sources differ from the profiled ones."""
+    from paper_2109_05496_amd import prof_summary
+    st = prof_summary.load_summary(os.path.join(ROOT, "profiles", names[0]))
+    pm = prof_summary.load_summary(os.path.join(ROOT, "profiles", names[1]))
+    if not st:
+        return None
+    per_unit = next((v["calls"] for k, v in st["kernels"].items() if marker in k), None)
+    if not per_unit:
+        return None
+    out = {}
+    for k, v in st["kernels"].items():
+        if not any(s in k for s in keep):
+            continue
+        p = pm["kernels"].get(k) if pm else None
+        d = {"launches_per_unit": round(v["calls"] / per_unit, 3), "avg_us": v["avg_us"],
+             "traffic_bytes": p["traffic_bytes"] if p else None,
+             "valu_issue_frac": p["valu_issue_frac"] if p else None}
+        if p and p["traffic_bytes"]:
+            gbs = p["traffic_bytes"] / (v["avg_us"] * 1e-6) / 1e9
+            d["hbm"] = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        out[k] = d
+    return out
+
+
+def _per_unit(figs, select, field):
+    """Sum over the selected kernels of launches per unit x field (None if any is missing)."""
+    tot = 0.0
+    for k, d in figs.items():
+        if select(k):
+            if d.get(field) is None:
+                return None
+            tot += d["launches_per_unit"] * d[field]
+    return tot
+
+
 def bench_adjoint(ctv, synth, torch, dev, reps=3):
     """16 x 512^2, type-1i, lambda 0.05, K = 50 with checkpoints every 10:
     forward (storing checkpoints) and hand-written backward."""
@@ -316,13 +371,41 @@ def bench_adjoint(ctv, synth, torch, dev, reps=3):
     ms_f = timed(fwd, reps, torch, stream)
     ms_b = timed(bwd, reps, torch, stream)
     px_it = B * m * n * K
+    # roofline of the backward: the unfused algorithmic bytes per backward
+    # pixel-iteration over the live backward time, and (from the committed
+    # profiles) each backward kernel's duration, measured traffic and VALU issue;
+    # launches per unit = per backward call
+    figs = profile_figures(ADJ_PROFILES, "adj_output_kernel", ("adj_", "lam_final", ", true>("))
+    alg_gbs = ADJ_BYTES_PER_PX_IT * px_it / (ms_b * 1e-3) / 1e9
+    traffic = _per_unit(figs, lambda k: True, "traffic_bytes") if figs else None
+    kern_us = _per_unit(figs, lambda k: True, "avg_us") if figs else None
+    step_k = next((k for k in figs if "adj_step_kernel" in k), None) if figs else None
+    sk = figs[step_k] if step_k else None
+    # SURVEY prices the backward against HBM; the profiles say which unit of the
+    # dominant (reverse-step) kernel is busier: VALU issue or HBM
+    limiter = None
+    if sk and sk.get("valu_issue_frac") is not None and sk.get("hbm"):
+        limiter = {"valu_issue_frac": sk["valu_issue_frac"], "hbm_frac": sk["hbm"]["frac"],
+                   "busier": "VALU issue" if sk["valu_issue_frac"] > sk["hbm"]["frac"] else "HBM"}
+    roof = {"bound": "hbm", "achieved": round(alg_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(alg_gbs / HBM_PEAK_GBS, 4), "bytes_per_px_it": ADJ_BYTES_PER_PX_IT,
+            "basis": "unfused model (recompute 56 + r history 16 + reverse step ~120 B per backward px-it) over "
+                     "the live backward time; fusion keeps the real traffic below it",
+            "traffic": round(traffic) if traffic is not None else None,
+            "hbm": ({"achieved": round(traffic / (ms_b * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(traffic / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "what": "measured bytes of one backward (profiles) over the live backward time"}
+                    if traffic is not None else None),
+            "dominant_kernel": step_k, "dominant_kernel_limiter": limiter,
+            "profiled_kernel_time_ms": round(kern_us / 1e3, 3) if kern_us is not None else None,
+            "kernels": figs}
     return {"workload": "16 x 512^2 complex64, type-1i, lambda 0.05, K=50, checkpoints every 10",
             "forward_ms": round(ms_f, 3), "backward_ms": round(ms_b, 3),
             "forward_Mpx_it_s": round(px_it / ms_f / 1e3, 1), "backward_Mpx_it_s": round(px_it / ms_b / 1e3, 1),
-            "backward_over_forward": round(ms_b / ms_f, 2)}
+            "backward_over_forward": round(ms_b / ms_f, 2), "roofline": roof}
 
 
-def bench_pr(ctv, synth, torch, dev, tuner, reps=2):
+def bench_pr(ctv, synth, torch, dev, tuner, reps=2, extras=True):
     """1024^2 object, 4 distances (1.0-2.5 mm, 532 nm, 4 um), Poisson 1000
     photons/pixel; 100 FISTA iterations x 20 FGP iterations (tau 0.01, gamma 1/4).
     The measurements are simulated with the library's own propagator."""
@@ -348,6 +431,41 @@ def bench_pr(ctv, synth, torch, dev, tuner, reps=2):
 
     ms = timed(run, reps, torch, stream)
     fgp_px_it = m * m * P["outer"] * P["inner"]
+    outer_us = ms * 1e3 / P["outer"]
+    # roofline of an outer iteration: the unfused algorithmic bytes per pixel
+    # over the live time, and per kernel (committed profiles; launches per unit
+    # = per outer iteration) the FFT side against its own 464 B per pixel
+    figs = profile_figures(PR_PROFILES, "fista_kernel", ("fft_", "fgp_", "fista", "transpose", "loss_final"))
+    is_fft = lambda k: "fft_" in k or "transpose" in k  # noqa: E731
+    alg_gbs = PR_BYTES_PER_PX_OUTER * m * m / (outer_us * 1e-6) / 1e9
+    fft_us = _per_unit(figs, is_fft, "avg_us") if figs else None
+    all_us = _per_unit(figs, lambda k: True, "avg_us") if figs else None
+    fft_traffic = _per_unit(figs, is_fft, "traffic_bytes") if figs else None
+    traffic = _per_unit(figs, lambda k: True, "traffic_bytes") if figs else None
+    fft = None
+    if fft_us:
+        fft_gbs = PR_FFT_BYTES_PER_PX_OUTER * m * m / (fft_us * 1e-6) / 1e9
+        fft = {"bound": "hbm", "achieved": round(fft_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(fft_gbs / HBM_PEAK_GBS, 4), "bytes_per_px": PR_FFT_BYTES_PER_PX_OUTER,
+               "traffic": round(fft_traffic) if fft_traffic is not None else None,
+               "hbm": ({"achieved": round(fft_traffic / (fft_us * 1e-6) / 1e9, 1),
+                        "frac": round(fft_traffic / (fft_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                       if fft_traffic is not None else None),
+               "us_per_outer_iteration": round(fft_us, 2),
+               "share_of_outer_iteration": round(fft_us / all_us, 4)}
+    roof = {"bound": "hbm", "achieved": round(alg_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(alg_gbs / HBM_PEAK_GBS, 4), "bytes_per_px_outer": PR_BYTES_PER_PX_OUTER,
+            "basis": "unfused model per outer iteration (FGP 20 x 56, FFT side 464 B per pixel) over the live time; "
+                     "the fused prox moves far less, so this ratio can exceed 1",
+            "traffic": round(traffic) if traffic is not None else None,
+            "hbm": ({"achieved": round(traffic / (all_us * 1e-6) / 1e9, 1),
+                     "frac": round(traffic / (all_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "what": "measured bytes of one outer iteration over its profiled kernel time"}
+                    if traffic is not None else None),
+            "fft": fft, "profiled_kernel_us_per_outer_iteration": round(all_us, 2) if all_us else None,
+            "kernels": figs}
+    if not extras:
+        return {"ms": round(ms, 3), "ms_per_outer_iteration": round(ms / P["outer"], 4), "roofline": roof}
 
     def loss_trace(accelerate):
         """Data term F after outer iterations 1, 10, 50, 100 (Algorithm 1 vs
@@ -375,7 +493,8 @@ def bench_pr(ctv, synth, torch, dev, tuner, reps=2):
     ms_ip = timed(lambda: ip_run(P["outer"]), reps, torch, stream)
     x0 = ctv.phase_retrieval_ip(y, P["distances"], P["wavelength"], P["pixel"], iters=0)
     return {"workload": "1024^2, D=4, 100 outer x 20 FGP iterations, type-1i, |x|<=1",
-            "prox_tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "ms": round(ms, 3), "ms_per_outer_iteration": round(ms / P["outer"], 4),
+            "prox_tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "ms": round(ms, 3),
+            "ms_per_outer_iteration": round(ms / P["outer"], 4), "roofline": roof,
             "fgp_Mpx_it_s_equiv": round(fgp_px_it / ms / 1e3, 1), "fft2_per_outer_iteration": 2 * len(P["distances"]) + 2,
             "data_term_fista_vs_ista": {"fista": loss_trace(True), "ista": loss_trace(False)},
             "phase_rmse_fista_vs_ista": {"fista": rmse_trace(fista_run("modulus")),
@@ -521,6 +640,17 @@ def bench_out_of_cache(ctv, synth, torch, dev, tuner, size=8192, iters=48, reps=
                                                        / HBM_PEAK_GBS, 3)}
 
 
+def copy_probe(torch, dev):
+    """Three 1 GiB device-to-device copies: the calibration of the byte
+    counters under rocprofv3. Returns the bytes copied each way."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 4
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -535,6 +665,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        # one secondary measurement alone (what its profiles are taken on)
+        tuner = Tuner(ctv, args.tuning, args.tuning_table)
+        res = (bench_adjoint(ctv, synth, torch, dev) if args.only == "adjoint"
+               else bench_pr(ctv, synth, torch, dev, tuner, extras=False))
+        if args.copy_probe:
+            copy_probe(torch, dev)
+        print(json.dumps({"only": args.only, args.only: res}), flush=True)
+        return
     c = synth.config2(0, size=args.size)
     m, n = c["b"].shape
     K = args.iters
@@ -658,12 +797,7 @@ def main():
         out["adjoint"] = bench_adjoint(ctv, synth, torch, dev)
         out["phase_retrieval"] = bench_pr(ctv, synth, torch, dev, tuner)
     if args.copy_probe:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes_each_way"] = src.numel() * 4
+        out["copy_probe_bytes_each_way"] = copy_probe(torch, dev)
     if args.save_tuning:
         ctv.tune_cache_save(args.save_tuning)
     if not args.no_cpu_baseline:

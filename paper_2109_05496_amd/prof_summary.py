@@ -1,14 +1,20 @@
 """Summarise rocprofv3 CSV output into the short text files kept under profiles/.
 
-    python -m paper_2109_05496_amd.prof_summary stats <kernel_stats.csv> <out.md> --cmd "<command>"
-    python -m paper_2109_05496_amd.prof_summary pmc <fetch_dir> <write_dir> <valu_dir> <out.md> --cmd "<command>"
+    python -m paper_2109_05496_amd.prof_summary stats <kernel_stats.csv> <out.md> --cmd "<command>" [--group G]
+    python -m paper_2109_05496_amd.prof_summary pmc <fetch_dir> <write_dir> <valu_dir> <out.md> --cmd "<command>" [--group G]
 
-The PMC summary carries a JSON block (per-dispatch FETCH_SIZE / WRITE_SIZE of
-the FGP tile kernel, scaled by the factors the same counters read for a 1 GiB
-device-to-device copy, and the VALU issue utilisation) together with the
-SHA-256 of the kernel sources it was measured on and the launch configuration
-(fusion depth and tile shape per TV kind) of the profiled runs; bench.py uses
-those numbers only while both still match.
+Both summaries end in a JSON block: per-kernel average durations (stats), or
+per-dispatch FETCH_SIZE / WRITE_SIZE scaled by the factors the same counters
+read for a 1 GiB device-to-device copy, and the VALU issue utilisation (pmc).
+The block records the kernel group it covers, the sources that build that
+group's kernels and their SHA-256, and (for the headline) the launch
+configuration of the profiled runs. bench.py uses a summary's numbers only
+while those sources are unchanged.
+
+Groups:
+  fgp      the forward FGP tile kernels (the headline step)
+  adjoint  the backward: reverse steps, the r-history recompute, the output pass
+  pr       the phase-retrieval loop: FFT passes, the FGP prox, the FISTA update
 """
 import argparse
 import collections
@@ -18,15 +24,33 @@ import json
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/fgp_forward.hip", "csrc/ctv_device.hpp", "csrc/capi.cpp", "csrc/batched.cpp")
+
+FGP_SOURCES = ("csrc/fgp_forward.hip", "csrc/fgp_sweep.hip", "csrc/ctv_tile.hpp", "csrc/ctv_device.hpp",
+               "csrc/ctv_kernels.hpp", "csrc/ctv_types.hpp", "csrc/capi.cpp", "csrc/batched.cpp")
+GROUPS = {
+    "fgp": {"sources": FGP_SOURCES,
+            "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_batched_kernel", "void ctv::fgp_sweep")},
+    "adjoint": {"sources": FGP_SOURCES + ("csrc/fgp_adjoint.hip", "csrc/adjoint.cpp", "csrc/ctv_adjoint.hpp"),
+                "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_sweep", "void ctv::(anonymous namespace)::adj_",
+                            "ctv::(anonymous namespace)::lam_final")},
+    "pr": {"sources": FGP_SOURCES + ("csrc/fft_pr.hip", "csrc/pr.cpp", "csrc/ctv_pr.hpp"),
+           "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_sweep", "void ctv::(anonymous namespace)::fft_",
+                       "ctv::(anonymous namespace)::fista", "ctv::(anonymous namespace)::transpose",
+                       "ctv::(anonymous namespace)::loss_final")},
+}
 
 
-def kernel_source_hash():
+def source_hash(sources):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(PKG, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def kernel_source_hash():
+    """Hash of the headline (fgp) group's sources."""
+    return source_hash(GROUPS["fgp"]["sources"])
 
 
 def _counters(d):
@@ -48,7 +72,11 @@ def _largest(v):
     return _mean([x for x in v if x >= 0.9 * top])
 
 
-def stats(csv_path, out, cmd, match=None, title=None):
+def _json_block(doc):
+    return ["", "```json", json.dumps(doc, indent=1), "```", ""]
+
+
+def stats(csv_path, out, cmd, match=None, title=None, group=None):
     rows = list(csv.DictReader(open(csv_path)))
     if match:
         keys = match.split("|")
@@ -57,10 +85,16 @@ def stats(csv_path, out, cmd, match=None, title=None):
     if match:
         head += [f"Kernels whose name contains: {', '.join('`%s`' % k for k in match.split('|'))}.", ""]
     lines = head + [f"Command: `{cmd}`", "",
-             "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+                    "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
     for r in rows:
         lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} % |")
+    if group:
+        doc = {"group": group, "sources": list(GROUPS[group]["sources"]),
+               "source_sha256": source_hash(GROUPS[group]["sources"]),
+               "kernels": {r["Name"]: {"calls": int(r["Calls"]), "avg_us": round(float(r["AverageNs"]) / 1e3, 3)}
+                           for r in rows if r["Name"].startswith(GROUPS[group]["kernels"])}}
+        lines += _json_block(doc)
     open(out, "w").write("\n".join(lines) + "\n")
 
 
@@ -77,19 +111,17 @@ def bench_tuning(log_path):
     raise ValueError(f"no bench.py result line in {log_path}")
 
 
-def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30,
-        kernel_prefix=("void ctv::fgp_col_kernel", "void ctv::fgp_batched_kernel"),
-        bench_log=None):
+def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, group="fgp", bench_log=None):
     fetch, write, valu = _counters(fetch_dir), _counters(write_dir), _counters(valu_dir)
     copy = next(k for k in fetch if "copyBuffer" in k)
     f_factor = copy_bytes / 1024.0 / _largest(fetch[copy]["FETCH_SIZE"])
     w_factor = copy_bytes / 1024.0 / _largest(write[copy]["WRITE_SIZE"])
     per_kernel = {}
     for k in sorted(fetch):
-        if not k.startswith(kernel_prefix):
+        if not k.startswith(GROUPS[group]["kernels"]):
             continue
         fk = _mean(fetch[k]["FETCH_SIZE"]) * f_factor * 1024
-        wk = _mean(write[k]["WRITE_SIZE"]) * w_factor * 1024
+        wk = _mean(write[k]["WRITE_SIZE"]) * w_factor * 1024 if k in write else None
         v = valu.get(k, {})
         util = None
         if v:
@@ -97,10 +129,13 @@ def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30,
             # over the 8 XCDs, each with 32 CUs x 4 SIMDs
             cycles_per_xcd = _mean(v["GRBM_GUI_ACTIVE"]) / 8.0
             util = 4.0 * _mean(v["SQ_INSTS_VALU"]) / (1024.0 * cycles_per_xcd)
-        per_kernel[k] = {"fetch_bytes": round(fk), "write_bytes": round(wk), "traffic_bytes": round(fk + wk),
+        per_kernel[k] = {"dispatches": len(fetch[k]["FETCH_SIZE"]), "fetch_bytes": round(fk),
+                         "write_bytes": None if wk is None else round(wk),
+                         "traffic_bytes": None if wk is None else round(fk + wk),
                          "valu_issue_frac": None if util is None else round(util, 3),
                          "valu_insts_per_dispatch": round(_mean(v["SQ_INSTS_VALU"])) if v else None}
-    doc = {"source_sha256": kernel_source_hash(), "fetch_factor": round(f_factor, 4),
+    doc = {"group": group, "sources": list(GROUPS[group]["sources"]),
+           "source_sha256": source_hash(GROUPS[group]["sources"]), "fetch_factor": round(f_factor, 4),
            "write_factor": round(w_factor, 4), "calibration": f"{copy} of {copy_bytes} bytes",
            "tuning": bench_tuning(bench_log) if bench_log else None, "kernels": per_kernel}
     lines = ["# rocprofv3 PMC summary", "", f"Command (one run per counter group): `{cmd}`", "",
@@ -108,16 +143,19 @@ def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30,
              f"{copy_bytes >> 30} GiB device-to-device copy in the same process "
              f"(FETCH_SIZE x {f_factor:.4f}, WRITE_SIZE x {w_factor:.4f}). VALU issue fraction = "
              "4 * SQ_INSTS_VALU / (1024 SIMDs * GRBM_GUI_ACTIVE / 8 XCDs).", "",
-             "| kernel | fetch (MB) | write (MB) | traffic (MB) | VALU issue |", "|---|---|---|---|---|"]
+             "| kernel | dispatches | fetch (MB) | write (MB) | traffic (MB) | VALU issue |", "|---|---|---|---|---|---|"]
     for k, d in per_kernel.items():
-        lines.append(f"| `{k}` | {d['fetch_bytes'] / 1e6:.1f} | {d['write_bytes'] / 1e6:.1f} | "
-                     f"{d['traffic_bytes'] / 1e6:.1f} | {d['valu_issue_frac']} |")
-    lines += ["", "```json", json.dumps(doc, indent=1), "```", ""]
+        wr = "-" if d["write_bytes"] is None else f"{d['write_bytes'] / 1e6:.1f}"
+        tr = "-" if d["traffic_bytes"] is None else f"{d['traffic_bytes'] / 1e6:.1f}"
+        lines.append(f"| `{k}` | {d['dispatches']} | {d['fetch_bytes'] / 1e6:.1f} | {wr} | {tr} | "
+                     f"{d['valu_issue_frac']} |")
+    lines += _json_block(doc)
     open(out, "w").write("\n".join(lines))
 
 
-def load_pmc(path):
-    """The JSON block of a PMC summary, or None if absent or measured on other sources."""
+def load_summary(path):
+    """The JSON block of a stats or PMC summary, or None if absent or measured
+    on other sources than the ones in the tree."""
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -125,7 +163,15 @@ def load_pmc(path):
         doc = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (IndexError, ValueError):
         return None
-    return doc if doc.get("source_sha256") == kernel_source_hash() else None
+    sources = doc.get("sources", GROUPS["fgp"]["sources"])
+    try:
+        ok = doc.get("source_sha256") == source_hash(sources)
+    except OSError:
+        return None
+    return doc if ok else None
+
+
+load_pmc = load_summary
 
 
 if __name__ == "__main__":
@@ -137,16 +183,19 @@ if __name__ == "__main__":
     s.add_argument("--cmd", required=True)
     s.add_argument("--match", default=None, help="'|'-separated substrings of the kernel names to keep")
     s.add_argument("--title", default=None)
+    s.add_argument("--group", default=None, choices=sorted(GROUPS),
+                   help="add the JSON block of this kernel group (average durations, source hash)")
     p = sub.add_parser("pmc")
     p.add_argument("fetch")
     p.add_argument("write")
     p.add_argument("valu")
     p.add_argument("out")
     p.add_argument("--cmd", required=True)
+    p.add_argument("--group", default="fgp", choices=sorted(GROUPS))
     p.add_argument("--bench-log", default=None, help="output of one of the profiled bench.py runs "
                                                       "(records the launch configuration it used)")
     a = ap.parse_args()
     if a.what == "stats":
-        stats(a.csv, a.out, a.cmd, a.match, a.title)
+        stats(a.csv, a.out, a.cmd, a.match, a.title, a.group)
     else:
-        pmc(a.fetch, a.write, a.valu, a.out, a.cmd, bench_log=a.bench_log)
+        pmc(a.fetch, a.write, a.valu, a.out, a.cmd, group=a.group, bench_log=a.bench_log)
