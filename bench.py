@@ -91,7 +91,7 @@ def parse():
                          "off = the library default")
     ap.add_argument("--tuning-table", default=TUNING_TABLE)
     ap.add_argument("--save-tuning", default=None, help="write the tuning table here at the end")
-    ap.add_argument("--only", choices=("adjoint", "pr"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "pr", "small"), default=None,
                     help="run only this secondary measurement, timed part only (for profiling it); prints "
                          "{\"only\": ..., <entry>: {...}} instead of the result line")
     return ap.parse_args()
@@ -668,8 +668,12 @@ def main():
     if args.only:
         # one secondary measurement alone (what its profiles are taken on)
         tuner = Tuner(ctv, args.tuning, args.tuning_table)
-        res = (bench_adjoint(ctv, synth, torch, dev) if args.only == "adjoint"
-               else bench_pr(ctv, synth, torch, dev, tuner, extras=False))
+        if args.only == "adjoint":
+            res = bench_adjoint(ctv, synth, torch, dev)
+        elif args.only == "small":
+            res = bench_small(ctv, synth, torch, dev, tuner)
+        else:
+            res = bench_pr(ctv, synth, torch, dev, tuner, extras=False)
         if args.copy_probe:
             copy_probe(torch, dev)
         print(json.dumps({"only": args.only, args.only: res}), flush=True)

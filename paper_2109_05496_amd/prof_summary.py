@@ -14,6 +14,7 @@ while those sources are unchanged.
 Groups:
   fgp      the forward FGP tile kernels (the headline step)
   adjoint  the backward: reverse steps, the r-history recompute, the output pass
+  small    the 64 x 64 latency case (tile kernels on a handful of CUs)
   pr       the phase-retrieval loop: FFT passes, the FGP prox, the FISTA update
 """
 import argparse
@@ -33,6 +34,7 @@ GROUPS = {
     "adjoint": {"sources": FGP_SOURCES + ("csrc/fgp_adjoint.hip", "csrc/adjoint.cpp", "csrc/ctv_adjoint.hpp"),
                 "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_sweep", "void ctv::(anonymous namespace)::adj_",
                             "ctv::(anonymous namespace)::lam_final")},
+    "small": {"sources": FGP_SOURCES, "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_single")},
     "pr": {"sources": FGP_SOURCES + ("csrc/fft_pr.hip", "csrc/pr.cpp", "csrc/ctv_pr.hpp"),
            "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_sweep", "void ctv::(anonymous namespace)::fft_",
                        "ctv::(anonymous namespace)::fista", "ctv::(anonymous namespace)::transpose",
@@ -133,7 +135,8 @@ def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, group="fgp
                          "write_bytes": None if wk is None else round(wk),
                          "traffic_bytes": None if wk is None else round(fk + wk),
                          "valu_issue_frac": None if util is None else round(util, 3),
-                         "valu_insts_per_dispatch": round(_mean(v["SQ_INSTS_VALU"])) if v else None}
+                         "valu_insts_per_dispatch": round(_mean(v["SQ_INSTS_VALU"])) if v else None,
+                         "counters": {c: round(_mean(x), 1) for c, x in sorted(v.items())}}
     doc = {"group": group, "sources": list(GROUPS[group]["sources"]),
            "source_sha256": source_hash(GROUPS[group]["sources"]), "fetch_factor": round(f_factor, 4),
            "write_factor": round(w_factor, 4), "calibration": f"{copy} of {copy_bytes} bytes",
