@@ -434,8 +434,9 @@ def bench_pr(ctv, synth, torch, dev, tuner, reps=2, extras=True):
     outer_us = ms * 1e3 / P["outer"]
     # roofline of an outer iteration: the unfused algorithmic bytes per pixel
     # over the live time, and per kernel (committed profiles; launches per unit
-    # = per outer iteration) the FFT side against its own 464 B per pixel
-    figs = profile_figures(PR_PROFILES, "fista_kernel", ("fft_", "fgp_", "fista", "transpose", "loss_final"))
+    # = per outer iteration, whose gradient runs the accumulate-inverse pass
+    # once) the FFT side against its own 464 B per pixel
+    figs = profile_figures(PR_PROFILES, "fft_acc_inverse_kernel", ("fft_", "fgp_", "transpose", "loss_final"))
     is_fft = lambda k: "fft_" in k or "transpose" in k  # noqa: E731
     alg_gbs = PR_BYTES_PER_PX_OUTER * m * m / (outer_us * 1e-6) / 1e9
     fft_us = _per_unit(figs, is_fft, "avg_us") if figs else None

@@ -4,7 +4,9 @@
 
 namespace ctv {
 
-enum FftPre { kPreNone = 0, kPreMulH = 1, kPreMulConjH = 2 };
+// kPreExtrapolate: the input is x + beta (x - in2) (Algorithm 1's z update),
+// also stored to zout at the same positions.
+enum FftPre { kPreNone = 0, kPreMulH = 1, kPreMulConjH = 2, kPreExtrapolate = 3 };
 // kPostAccumulateAll: acc (+)= sum over n_acc images of conj(H_img) * transform
 // (the images are looped inside one launch, so there is no race on acc).
 // kPostReplace: sqrt(y) times the unit phasor of the value (the measured-modulus
@@ -35,6 +37,9 @@ struct FftArgs {
   int accumulate;         // 0: acc = w, 1: acc += w
   int n_acc;              // images summed by kPostAccumulateAll
   int constr;             // kPostProjC: 0 = C^{m x n} (store), 1 = |x| <= 1
+  const float2* in2;      // kPreExtrapolate: the previous iterate (layout and stride of in)
+  float2* zout;           // kPreExtrapolate: where the extrapolated input is stored
+  float beta;             // kPreExtrapolate: the momentum weight
 };
 
 bool fft_size_ok(int v);
@@ -59,7 +64,6 @@ hipError_t launch_fft_acc_inverse(FftArgs a, int N, long long lines, hipStream_t
 hipError_t launch_twiddles(float2* tw, int N, hipStream_t s);
 hipError_t launch_transfer_t(float2* Ht, int m, int n, double dist, double wavelength, double pixel, hipStream_t s);
 hipError_t launch_sqrt_y(const float* y, float* sy, float2* syc, long long total, hipStream_t s);
-hipError_t launch_fista(const float2* x, float2* xprev, float2* z, float beta, long long total, hipStream_t s);
 hipError_t launch_loss_final(const double* partial, int count, float* out, hipStream_t s);
 hipError_t launch_copy_c(const float2* a, float2* b, long long total, hipStream_t s);
 // Line search helpers: out[j] = sum_i partial[i * stride + j] (j < width <= 64, float64,

@@ -183,14 +183,25 @@ __device__ __forceinline__ void post_block(const FftArgs& a, int img, long long 
 }
 
 // Loads CNT elements of image `img` at p0 + r * STRIDE into v, multiplied by H
-// or conj(H) at the same positions when a.pre asks for it (all loads issued
-// before the first use).
+// or conj(H) at the same positions, or extrapolated as x + beta (x - x_prev)
+// (and stored), when a.pre asks for it (all loads issued before the first use).
 template <int CNT, int STRIDE>
 __device__ __forceinline__ void load_pre(const FftArgs& a, int img, long long p0, float2 (&v)[16]) {
   const float2* in = a.in + (long long)img * a.in_stride + p0;
 #pragma unroll
   for (int r = 0; r < CNT; ++r) v[r] = in[r * STRIDE];
-  if (a.pre != kPreNone) {
+  if (a.pre == kPreExtrapolate) {
+    const float2* xp = a.in2 + (long long)img * a.in_stride + p0;
+    float2* zo = a.zout + (long long)img * a.in_stride + p0;
+    float2 u[16];
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) u[r] = xp[r * STRIDE];
+#pragma unroll
+    for (int r = 0; r < CNT; ++r) {
+      v[r] = make_float2(fmaf(a.beta, v[r].x - u[r].x, v[r].x), fmaf(a.beta, v[r].y - u[r].y, v[r].y));
+      zo[r * STRIDE] = v[r];
+    }
+  } else if (a.pre != kPreNone) {
     const float2* H = a.H + (long long)img * a.H_stride + p0;
     float2 h[16];
 #pragma unroll
@@ -703,16 +714,6 @@ __global__ __launch_bounds__(256) void sqrt_y_kernel(const float* __restrict__ y
   if (syc) syc[p] = make_float2(v, 0.0f);
 }
 
-// z = x + beta (x - x_prev) (Algorithm 1, line 5); also copies x to x_prev.
-__global__ __launch_bounds__(256) void fista_kernel(const float2* __restrict__ x, float2* __restrict__ xprev,
-                                                    float2* __restrict__ z, float beta, long long total) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= total) return;
-  const float2 xv = x[p], xp = xprev[p];
-  z[p] = make_float2(fmaf(beta, xv.x - xp.x, xv.x), fmaf(beta, xv.y - xp.y, xv.y));
-  xprev[p] = xv;
-}
-
 // Sum of partial[i * stride + j] over i < count by one wave: lane l adds the
 // terms l, l + 64, ... in order, then a fixed butterfly combines the lanes,
 // so the summation order (and the result) is the same on every run.
@@ -941,11 +942,6 @@ hipError_t launch_transfer_t(float2* Ht, int m, int n, double dist, double wavel
 
 hipError_t launch_sqrt_y(const float* y, float* sy, float2* syc, long long total, hipStream_t s) {
   hipLaunchKernelGGL(sqrt_y_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, y, sy, syc, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_fista(const float2* x, float2* xprev, float2* z, float beta, long long total, hipStream_t s) {
-  hipLaunchKernelGGL(fista_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, xprev, z, beta, total);
   return hipGetLastError();
 }
 

@@ -121,10 +121,24 @@ FftArgs line_args(const float2* in, float2* out, const float2* tw, long long str
 // Spectrum (transposed, [n][m]) of a natural-layout [m][n] image: a pass along
 // n, then a column pass along m that writes the transposed layout, with
 // epilogue `last` (in/out/tw filled here).
-ctv_status fft2_to_t(const Ctx& c, const float2* in, float2* out, FftArgs last) {
+// The momentum step of Algorithm 1 (line 5) done in the first pass of the
+// next transform: z = x + beta (x - x_prev), stored to z on the way.
+struct Extrapolate {
+  const float2* x_prev;
+  float beta;
+  float2* z;
+};
+
+ctv_status fft2_to_t(const Ctx& c, const float2* in, float2* out, FftArgs last, const Extrapolate* ex = nullptr) {
   float2* t1 = c.at(c.L.t1);
   float2* t2 = c.at(c.L.t2);
   FftArgs a = line_args(in, t1, c.at(c.L.tw_n), c.px);
+  if (ex) {
+    a.pre = kPreExtrapolate;
+    a.in2 = ex->x_prev;
+    a.beta = ex->beta;
+    a.zout = ex->z;
+  }
   CTV_TRY(launch_fft_lines(a, c.n, c.m, -1, 1, c.s), "fft (rows)");
   last.in = t1;
   last.out = out;
@@ -193,7 +207,10 @@ ctv_status accumulate_spectra(const Ctx& c, const float2* r, float2* acc) {
 }
 
 // grad F at z (Eq. 27 summed over d). post_step: out = z - gamma grad; else out = grad.
-ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, float gamma, float* loss) {
+// With ex, z is first formed from the two latest iterates (z given as x, ex->z
+// receives it).
+ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, float gamma, float* loss,
+                    const Extrapolate* ex = nullptr) {
   const float inv = 1.0f / (float)((double)c.m * c.n);
   float2* xh = c.at(c.L.xh);
   float2* t1 = c.at(c.L.t1);
@@ -201,8 +218,9 @@ ctv_status gradient(const Ctx& c, const float2* z, float2* out, bool post_step, 
   float2* acc = c.at(c.L.acc);
   double* part = reinterpret_cast<double*>(c.ws + c.L.part);
   const int rb = residual_blocks(c.m, c.n);
-  ctv_status st = fft2_to_t(c, z, xh, epilogue(kPostStore, 1.0f));
+  ctv_status st = fft2_to_t(c, z, xh, epilogue(kPostStore, 1.0f), ex);
   if (st) return st;
+  if (ex) z = ex->z;
   // A_d z = IFFT2(H_d Z) for all d (one shared input spectrum), then the
   // residual bracket of Eq. (27) in t2[d]
   FftArgs a = line_args(xh, t1, c.at(c.L.tw_m), c.px);
@@ -462,8 +480,8 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   } else {
     CTV_TRY(launch_copy_c(reinterpret_cast<const float2*>(x), xcur, c.px, c.s), "copy");
   }
+  // x_{-1} = x_0 (the first momentum weight is 0, and x_0 - x_{-1} must be finite)
   CTV_TRY(launch_copy_c(xcur, xprev, c.px, c.s), "copy");
-  CTV_TRY(launch_copy_c(xcur, z, c.px, c.s), "copy");
   float gamma = p->gamma > 0.0f ? p->gamma : 1.0f / (float)c.D;
   Tiling tl;
   st = choose_tiling(&p->inner, m, n, 1, &tl, p->inner.schedule != CTV_S_FLOW);
@@ -481,8 +499,10 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
   float* wnext = wcur + align_up(state_bytes(1, m, n)) / 4;
   bool have_warm = false;
 
-  // x_k = prox_{gamma R}(v): Algorithm 2 with lambda = tau gamma from q_0 = 0 or
-  // the warm dual; with the warm start the last launch also stores its state.
+  // x_k = prox_{gamma R}(v) into xnew: Algorithm 2 with lambda = tau gamma from
+  // q_0 = 0 or the warm dual; with the warm start the last launch also stores
+  // its state.
+  float2* xnew = xprev;
   auto prox = [&](float lam) -> ctv_status {
     // A weight the denoiser rejects (0 < tau gamma < 1e-12, reachable only by
     // backtracking far) is taken as 0: P_C alone, within 6 tau gamma per pixel.
@@ -494,7 +514,7 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
       const bool last = (kk + Tl == Kin);
       float* dst = last ? (warm ? wnext : nullptr) : (src == fA ? fB : fA);
       ctv_status e = fgp_launch(&p->inner, tl, 1, m, n, reinterpret_cast<const float*>(v), nullptr, &lam, beta, kk,
-                                Tl, src, dst, last ? reinterpret_cast<float*>(xcur) : nullptr, c.s);
+                                Tl, src, dst, last ? reinterpret_cast<float*>(xnew) : nullptr, c.s);
       if (e) return e;
       src = dst;
       kk += Tl;
@@ -502,16 +522,22 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
     return CTV_OK;
   };
 
+  // xcur / xprev hold the two latest iterates; z_k = x_{k-1} + b_k (x_{k-1} - x_{k-2})
+  // (Algorithm 1, lines 4-5) is formed in the first pass of the gradient's
+  // transform, and the prox writes x_k over x_{k-2}.
   double t = 1.0;
+  float b = 0.0f;  // z_1 = x_0
   for (int k = 0; k < p->outer_iters; ++k) {
+    const Extrapolate ex{xprev, b, z};
+    xnew = xprev;
     if (!p->line_search) {
       // v = z_k - gamma grad F(z_k)  (Algorithm 1, line 3's argument)
-      st = gradient(c, z, v, true, gamma, loss_trace ? loss_trace + k : nullptr);
+      st = gradient(c, xcur, v, true, gamma, loss_trace ? loss_trace + k : nullptr, &ex);
       if (st) return st;
       st = prox((float)((double)p->tau * gamma));
       if (st) return st;
     } else {
-      st = gradient(c, z, g, false, 0.0f, loss_trace ? loss_trace + k : nullptr);
+      st = gradient(c, xcur, g, false, 0.0f, loss_trace ? loss_trace + k : nullptr, &ex);
       if (st) return st;
       CTV_TRY(launch_sum_d(reinterpret_cast<const double*>(c.ws + c.L.part), c.D * residual_blocks(m, n), 1, 1,
                            lsv, c.s), "loss");
@@ -520,9 +546,9 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
         st = prox((float)((double)p->tau * gamma));
         if (st) return st;
         if (trial == p->ls_max_trials - 1) break;
-        st = data_term(c, xcur, lsv + 1);
+        st = data_term(c, xnew, lsv + 1);
         if (st) return st;
-        CTV_TRY(launch_ls_dots(g, xcur, z, c.px, lsp, c.s), "line search");
+        CTV_TRY(launch_ls_dots(g, xnew, z, c.px, lsp, c.s), "line search");
         CTV_TRY(launch_sum_d(lsp, kLsBlocks, 2, 2, lsv + 2, c.s), "line search");
         double h[4];
         CTV_TRY(hipMemcpyAsync(h, lsv, sizeof(h), hipMemcpyDeviceToHost, c.s), "line search readback");
@@ -539,10 +565,11 @@ ctv_status pr_prox_grad(const pr_params* p, int32_t m, int32_t n, const float* y
                             2 * c.px, c.s), "warm start");
       have_warm = true;
     }
-    // t_{k+1}, z_{k+1} = x_k + ((t_k - 1)/t_{k+1}) (x_k - x_{k-1})  (lines 4-5)
+    // t_{k+1} and the weight (t_k - 1)/t_{k+1} of z_{k+1} = x_k + b (x_k - x_{k-1})
+    // (lines 4-5; z_{k+1} is formed by the next gradient)
     const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    const float b = p->accelerate ? (float)((t - 1.0) / tn) : 0.0f;
-    CTV_TRY(launch_fista(xcur, xprev, z, b, c.px, c.s), "fista step");
+    b = p->accelerate ? (float)((t - 1.0) / tn) : 0.0f;
+    std::swap(xcur, xprev);
     t = tn;
   }
   CTV_TRY(launch_copy_c(xcur, reinterpret_cast<float2*>(x), c.px, c.s), "copy");

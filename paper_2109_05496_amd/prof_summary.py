@@ -15,7 +15,7 @@ Groups:
   fgp      the forward FGP tile kernels (the headline step)
   adjoint  the backward: reverse steps, the r-history recompute, the output pass
   small    the 64 x 64 latency case (tile kernels on a handful of CUs)
-  pr       the phase-retrieval loop: FFT passes, the FGP prox, the FISTA update
+  pr       the phase-retrieval loop: FFT passes (the FISTA update inside the first) and the FGP prox
 """
 import argparse
 import collections
@@ -37,8 +37,7 @@ GROUPS = {
     "small": {"sources": FGP_SOURCES, "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_single")},
     "pr": {"sources": FGP_SOURCES + ("csrc/fft_pr.hip", "csrc/pr.cpp", "csrc/ctv_pr.hpp"),
            "kernels": ("void ctv::fgp_col_kernel", "void ctv::fgp_sweep", "void ctv::(anonymous namespace)::fft_",
-                       "ctv::(anonymous namespace)::fista", "ctv::(anonymous namespace)::transpose",
-                       "ctv::(anonymous namespace)::loss_final")},
+                       "ctv::(anonymous namespace)::transpose", "ctv::(anonymous namespace)::loss_final")},
 }
 
 

@@ -233,12 +233,14 @@ def test_line_search_and_warm_start_config5():
     assert float(x.abs().max()) <= 1 + 1e-6
 
 
-@pytest.mark.parametrize("m,n,D", [(64, 64, 6), (32, 32, 9), (16, 64, 3), (64, 16, 2), (128, 64, 5)])
+@pytest.mark.parametrize("m,n,D", [(64, 64, 6), (32, 32, 9), (16, 64, 3), (64, 16, 2), (128, 64, 5),
+                                   (2048, 64, 2), (64, 2048, 2), (4096, 32, 2), (32, 4096, 2)])
 def test_gradient_distance_counts_and_short_lines(m, n, D):
     """The gradient's last forward pass sums conj(H_d) over the distances and
     inverts the sum in one launch, up to four distances side by side: more
-    than four distances (a running sum per group), and lines shorter than 32
-    (the separate accumulate pass) against the oracle."""
+    than four distances (a running sum per group), lines shorter than 32
+    (the separate accumulate pass), and the longest lines (2048 and 4096 in
+    either direction, one or two line slots per block) against the oracle."""
     big = synth.config5_object(seed=11, size=max(m, n), n_shapes=10, sigma_px=2.0)
     truth = big[:m, :n]
     dists = [P5["distances"][d % 4] * (1.0 + 0.25 * (d // 4)) for d in range(D)]
