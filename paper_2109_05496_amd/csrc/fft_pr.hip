@@ -212,40 +212,69 @@ __device__ __forceinline__ void load_pre(const FftArgs& a, int img, long long p0
   }
 }
 
-template <int DIR>
-__device__ __forceinline__ float2 tw_load(const float2* __restrict__ tw, int idx) {
-  const float2 w = tw[idx];
-  return DIR < 0 ? w : conjf2(w);
-}
-
 // One Stockham pass of radix R over an LDS line (Ns = size of the sub-transforms
 // already done); the thread handles butterflies j0, j0 + TPL, ... < N/R.
 // LDS index with one pad element per 16: the strided writes of a pass spread
 // over the banks instead of landing on one.
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
+// exp(-+2 pi i idx / N) (sign by DIR) for 0 <= idx < N from the half table
+// twh[k] = exp(-2 pi i k / N), k < N/2, staged in LDS: the second half is the
+// first negated.
+template <int N, int DIR>
+__device__ __forceinline__ float2 tw_half(const float2* twh, int idx) {
+  const float2 w = twh[idx & (N / 2 - 1)];
+  const unsigned neg = (unsigned)(idx & (N / 2)) << (31 - __builtin_ctz(N / 2));  // sign bit for the second half
+  const float x = __uint_as_float(__float_as_uint(w.x) ^ neg);
+  const float y = __uint_as_float(__float_as_uint(w.y) ^ neg);
+  return DIR < 0 ? make_float2(x, y) : make_float2(x, -y);
+}
+
+// The first N/2 twiddles staged into LDS by NT threads: the loads (issued
+// before the caller's own) and the LDS stores (after them) are separate, so
+// waiting for the twiddles does not hold back the data loads.
+template <int N, int NT>
+struct TwStage {
+  static constexpr int K = (N / 2 + NT - 1) / NT;
+  float2 v[K];
+  __device__ __forceinline__ void fetch(const float2* __restrict__ tw) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int idx = (int)threadIdx.x + i * NT;
+      v[i] = idx < N / 2 ? tw[idx] : make_float2(0.0f, 0.0f);
+    }
+  }
+  __device__ __forceinline__ void store(float2* twh) const {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int idx = (int)threadIdx.x + i * NT;
+      if (idx < N / 2) twh[idx] = v[i];
+    }
+  }
+};
+
 template <int N, int R, int DIR, int TPL>
-__device__ __forceinline__ void pass_lds(const float2* L, float2 (&v)[16], int j, int Ns,
-                                         const float2* __restrict__ tw) {
+__device__ __forceinline__ void pass_lds(const float2* L, float2 (&v)[16], int j, int Ns, const float2* twh) {
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = L[pidx(j + r * (N / R))];
   const int k = j & (Ns - 1);
   if (k) {
     const int step = (N / (Ns * R)) * k;
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw_load<DIR>(tw, r * step));
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw_half<N, DIR>(twh, r * step));
   }
   dft<R, DIR>(v);
 }
 
 // The FFT of one line from the first radix-16 pass on, the thread's 16 inputs
-// (line positions lt + r * N/16) already in v; the 16 outputs of the last
+// (line positions lt + r * N/16) already in v, twiddles from the LDS half
+// table twh (visible after the first barrier here); the 16 outputs of the last
 // pass are returned in o[] with their positions within the line in pos[].
 // OPAQUE_LANE: take the lane index through an empty asm, so that a second
 // transform in the same kernel recomputes its LDS and twiddle offsets instead
 // of keeping the first one's alive in registers.
 template <int N, int DIR, bool OPAQUE_LANE = false>
-__device__ __forceinline__ void line_fft_regs(const FftArgs& a, float2* sl, float2 (&v)[16], float2 (&o)[16],
+__device__ __forceinline__ void line_fft_regs(float2* sl, const float2* twh, float2 (&v)[16], float2 (&o)[16],
                                               int (&pos)[16]) {
   constexpr int TPL = N / 16;                  // threads per line
   constexpr int L = (N == 32) ? 5 : (N == 64) ? 6 : (N == 128) ? 7 : (N == 256) ? 8 : (N == 512) ? 9
@@ -265,7 +294,7 @@ __device__ __forceinline__ void line_fft_regs(const FftArgs& a, float2* sl, floa
   for (int p = 1; p < NPASS; ++p) {
     const bool last = (p == NPASS - 1);
     if (p < P16) {
-      pass_lds<N, 16, DIR, TPL>(sl, v, lt, Ns, a.tw);
+      pass_lds<N, 16, DIR, TPL>(sl, v, lt, Ns, twh);
       const int k = lt & (Ns - 1);
       const int d = (lt - k) * 16 + k;
       if (!last) {
@@ -288,7 +317,7 @@ __device__ __forceinline__ void line_fft_regs(const FftArgs& a, float2* sl, floa
       for (int bb = 0; bb < B; ++bb) {
         float2 w[16];
         const int j = lt + bb * TPL;
-        pass_lds<N, RR, DIR, TPL>(sl, w, j, Ns, a.tw);
+        pass_lds<N, RR, DIR, TPL>(sl, w, j, Ns, twh);
         const int k = j & (Ns - 1);
         const int d = (j - k) * RR + k;
 #pragma unroll
@@ -302,28 +331,27 @@ __device__ __forceinline__ void line_fft_regs(const FftArgs& a, float2* sl, floa
   }
 }
 
-// The FFT of one line (image `img`, line `line`) up to the last pass, whose 16
-// outputs per thread are returned in o[] with their positions within the line.
-// FROM_LDS: the line is already staged in sl (natural order, pidx positions)
-// and the first pass reads it from there instead of global memory.
-template <int N, int DIR, bool FROM_LDS = false>
-__device__ __forceinline__ void line_fft(const FftArgs& a, int img, long long line, bool live, float2* sl,
-                                         float2 (&o)[16], int (&pos)[16]) {
-  constexpr int TPL = N / 16;                  // threads per line
+// The 16 inputs of this thread's first pass for line `line` of image `img`
+// (positions lt + r * N/16), with the pre-operation of a.pre; zeros if !live.
+template <int N>
+__device__ __forceinline__ void line_load(const FftArgs& a, int img, long long line, bool live, float2 (&v)[16]) {
+  constexpr int TPL = N / 16;
   const int lt = threadIdx.x % TPL;
-  const long long rowbase = line * N;
-  float2 v[16];
-  // pass 1: radix 16 straight from global memory (Ns = 1, no twiddles)
-  if (FROM_LDS) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = sl[pidx(lt + r * TPL)];
-  } else if (live) {
-    load_pre<16, TPL>(a, img, rowbase + lt, v);
+  if (live) {
+    load_pre<16, TPL>(a, img, line * N + lt, v);
   } else {
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
   }
-  line_fft_regs<N, DIR>(a, sl, v, o, pos);
+}
+
+// The same inputs from a line staged in LDS (natural order, pidx positions).
+template <int N>
+__device__ __forceinline__ void line_from_lds(const float2* sl, float2 (&v)[16]) {
+  constexpr int TPL = N / 16;
+  const int lt = threadIdx.x % TPL;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = sl[pidx(lt + r * TPL)];
 }
 
 template <int N, int DIR, bool ACCALL>
@@ -332,20 +360,25 @@ __global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
   constexpr int LPB = kThreads / TPL;          // lines per block
   constexpr int LS = N + N / 16;               // padded LDS line length
   __shared__ float2 s[LPB * LS];
+  __shared__ float2 twh[N / 2];
   __shared__ double red[kThreads / 64];
   const int li = threadIdx.x / TPL;
   const long long line = (long long)blockIdx.x * LPB + li;
   const bool live = line < a.lines;
   float2* sl = s + li * LS;
-  float2 o[16];
+  float2 o[16], v[16];
   int pos[16];
+  TwStage<N, kThreads> tws;
+  tws.fetch(a.tw);
   if (ACCALL) {
     // acc (+)= sum over the n_acc images of conj(H_img) * FFT(line of image img)
     float2 sum[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) sum[r] = make_float2(0.0f, 0.0f);
     for (int img = 0; img < a.n_acc; ++img) {
-      line_fft<N, DIR>(a, img, line, live, sl, o, pos);
+      line_load<N>(a, img, line, live, v);
+      if (img == 0) tws.store(twh);
+      line_fft_regs<N, DIR>(sl, twh, v, o, pos);
       if (live) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -364,7 +397,9 @@ __global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
     return;
   }
   const int img = blockIdx.y;
-  line_fft<N, DIR>(a, img, line, live, sl, o, pos);
+  line_load<N>(a, img, line, live, v);
+  tws.store(twh);
+  line_fft_regs<N, DIR>(sl, twh, v, o, pos);
   double loss = 0.0;
   if (live) post_block<16>(a, img, line * N, pos, o, loss);
   if (a.post == kPostResidual) {
@@ -398,19 +433,24 @@ __global__ __launch_bounds__(kThreads) void fft_acc_inverse_kernel(FftArgs a) {
   constexpr int LPB = acc_lines_per_block<N>();
   constexpr int LS = N + N / 16;
   __shared__ float2 s[SLOTS * LS];
+  __shared__ float2 twh[N / 2];
   const int slot = threadIdx.x / TPL;
   const int g = slot % G, li = slot / G;
   const int lt = threadIdx.x % TPL;
   const long long line = (long long)blockIdx.x * LPB + li;
   const bool live = line < a.lines;
   float2* sl = s + slot * LS;
-  float2 sum[16], o[16];
+  float2 sum[16], o[16], v[16];
   int pos[16];
+  TwStage<N, kThreads> tws;
+  tws.fetch(a.tw);
   const int rounds = ONE ? 1 : (a.n_acc + G - 1) / G;  // the same for every group: barriers match
   for (int it = 0; it < rounds; ++it) {
     const int img = g + it * G;
     const bool act = live && img < a.n_acc;
-    line_fft<N, -1>(a, act ? img : 0, line, act, sl, o, pos);
+    line_load<N>(a, act ? img : 0, line, act, v);
+    if (it == 0) tws.store(twh);
+    line_fft_regs<N, -1>(sl, twh, v, o, pos);
     float2 h[16];
     const float2* H = a.H + (long long)(act ? img : 0) * a.H_stride + line * N;
 #pragma unroll
@@ -426,7 +466,6 @@ __global__ __launch_bounds__(kThreads) void fft_acc_inverse_kernel(FftArgs a) {
   for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = sum[r];
   __syncthreads();
   const float2* s0 = s + (li * G) * LS;
-  float2 v[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int p = pidx(lt + r * TPL);
@@ -435,7 +474,7 @@ __global__ __launch_bounds__(kThreads) void fft_acc_inverse_kernel(FftArgs a) {
     for (int gg = 1; gg < G; ++gg) t = cadd(t, s0[gg * LS + p]);
     v[r] = t;
   }
-  line_fft_regs<N, 1, true>(a, sl, v, o, pos);
+  line_fft_regs<N, 1, true>(sl, twh, v, o, pos);
   if (live && g == 0) {
     float2* out = a.out + line * N;
 #pragma unroll
@@ -553,8 +592,12 @@ template <int N, int DIR, int CB>
 __global__ __launch_bounds__(CB * (N / 16)) void fft_col_kernel(FftArgs a) {
   constexpr int TPL = N / 16;
   constexpr int NT = CB * TPL;
-  constexpr int LS = N + N / 16 + 1;  // padded line; the odd pitch spreads the staging writes over banks
+  // padded line: with a pitch of 4 (mod 32) elements beyond the pidx length the
+  // column-staging accesses (CB columns x consecutive rows per wave) measured the
+  // fewest LDS bank conflicts (pitches +0, +1, +8, +17 had 1.1-3x as many)
+  constexpr int LS = N + N / 16 + 4;
   __shared__ float2 s[CB * LS];
+  __shared__ float2 twh[N / 2];
   __shared__ double red[(NT + 63) / 64];
   const long long W = a.lines;
   const int cl = threadIdx.x / TPL;
@@ -563,10 +606,14 @@ __global__ __launch_bounds__(CB * (N / 16)) void fft_col_kernel(FftArgs a) {
   const bool live = col < W;
   float2* sl = s + cl * LS;
   const int img = blockIdx.y;
+  TwStage<N, NT> tws;
+  tws.fetch(a.tw);
   stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, grp, s);
-  float2 o[16];
+  tws.store(twh);
+  float2 o[16], v[16];
   int pos[16];
-  line_fft<N, DIR, true>(a, img, col, live, sl, o, pos);
+  line_from_lds<N>(sl, v);
+  line_fft_regs<N, DIR>(sl, twh, v, o, pos);
   double loss = 0.0;
   if (live) post_block<16>(a, img, col * N, pos, o, loss);
   if (a.post == kPostResidual) {
@@ -591,15 +638,17 @@ __global__ __launch_bounds__(CB * (N / 16)) void fft_col_kernel(FftArgs a) {
 // residual never goes to memory. Column c of the image is row c of the
 // natural-layout image, so sqrt(y) is read at c * N + k. Columns are staged
 // through LDS for row-contiguous loads and stores, as in fft_col_kernel.
-// Two blocks share a CU (the LDS fits two), so at most 128 VGPRs per lane.
+// Two blocks share a CU where the LDS fits two (N <= 2048), so at most 128
+// VGPRs per lane there.
 template <int N>
-__global__ __launch_bounds__(col_block<N>() * (N / 16)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(col_block<N>() * (N / 16)) __attribute__((amdgpu_waves_per_eu(N <= 2048 ? 4 : 2)))
 void fft_col_roundtrip_kernel(FftArgs a) {
   constexpr int TPL = N / 16;
   constexpr int CB = col_block<N>();
   constexpr int NT = CB * TPL;
-  constexpr int LS = N + N / 16 + 1;
+  constexpr int LS = N + N / 16 + 4;  // as in fft_col_kernel
   __shared__ float2 s[CB * LS];
+  __shared__ float2 twh[N / 2];
   __shared__ double red[(NT + 63) / 64];
   const long long W = a.lines;
   const int cl = threadIdx.x / TPL;
@@ -608,10 +657,17 @@ void fft_col_roundtrip_kernel(FftArgs a) {
   const bool live = col < W;
   float2* sl = s + cl * LS;
   const int img = blockIdx.y;
+  TwStage<N, NT> tws;
+  tws.fetch(a.tw);
   stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, grp, s);
+  tws.store(twh);
   float2 o[16];
   int pos[16];
-  line_fft<N, 1, true>(a, img, col, live, sl, o, pos);
+  {
+    float2 v[16];
+    line_from_lds<N>(sl, v);
+    line_fft_regs<N, 1>(sl, twh, v, o, pos);
+  }
   __syncthreads();  // every thread's last inverse pass has read its line
 #pragma unroll
   for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = o[r];
@@ -636,7 +692,7 @@ void fft_col_roundtrip_kernel(FftArgs a) {
     v[r] = make_float2(ph.x * res, ph.y * res);
     if (live) loss += 0.5 * (double)res * (double)res;
   }
-  line_fft_regs<N, -1, true>(a, sl, v, o, pos);
+  line_fft_regs<N, -1, true>(sl, twh, v, o, pos);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < 16; ++r) sl[pidx(pos[r])] = o[r];
