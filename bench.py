@@ -493,6 +493,16 @@ def bench_pr(ctv, synth, torch, dev, tuner, reps=2, extras=True):
 
     ms_ip = timed(lambda: ip_run(P["outer"]), reps, torch, stream)
     x0 = ctv.phase_retrieval_ip(y, P["distances"], P["wavelength"], P["pixel"], iters=0)
+
+    def kind_run(kind, constraint):
+        return ctv.phase_retrieval(y, P["distances"], P["wavelength"], P["pixel"], tau=P["tau"], gamma=P["gamma"],
+                                   outer=P["outer"], inner=P["inner"], kind=kind, alpha=P["alpha"],
+                                   constraint=constraint)
+
+    by_kind = {"what": "phase RMSE (rad) after 100 outer iterations with each TV kind, without (TV) and with (CTV) "
+                       "the constraint |x| <= 1: the comparison of Fig. 4 on the synthetic object",
+               **{k: {c_name: round(phase_rmse(kind_run(k, c).cpu().numpy(), truth), 5)
+                      for c_name, c in (("tv", "none"), ("ctv", "modulus"))} for k in ("1i", "1a", "2i", "2a")}}
     return {"workload": "1024^2, D=4, 100 outer x 20 FGP iterations, type-1i, |x|<=1",
             "prox_tuning": {"fuse": T, "tile": [tw, tr], "source": source}, "ms": round(ms, 3),
             "ms_per_outer_iteration": round(ms / P["outer"], 4), "roofline": roof,
@@ -507,7 +517,43 @@ def bench_pr(ctv, synth, torch, dev, tuner, reps=2, extras=True):
                           "backprop_rmse": round(phase_rmse(x0.cpu().numpy(), truth), 5),
                           "ctv": rmse_trace(fista_run("modulus")), "tv": rmse_trace(fista_run("none")),
                           "ip": rmse_trace(ip_run), "ip_ms_100_iterations": round(ms_ip, 3),
-                          "ip_fft2_per_iteration": 4 * len(P["distances"])}}
+                          "ip_fft2_per_iteration": 4 * len(P["distances"])},
+            "tv_ctv_by_kind": by_kind,
+            "paper_simulation": paper_simulation(ctv, synth, torch, dev)}
+
+
+def paper_simulation(ctv, synth, torch, dev):
+    """The simulated experiment of Section VI-A with synthetic stand-ins: a
+    256^2 pure phase object (phase in [0, pi)), pixel 5 um, 500 nm, one
+    distance of 5 mm, 10 % Gaussian intensity noise; IP, TV and CTV (type-I
+    anisotropic, 10 FGP iterations per prox) from the back-propagated field,
+    phase RMSE after 10 / 50 / 100 iterations (Fig. 2's comparison), and CTV
+    after 100 iterations for several tau (Fig. 6's question)."""
+    import numpy as np
+    S = synth.PR_PAPER_SIM
+    truth = synth.phase_object(seed=0, size=S["size"])
+    fields = ctv.pr_forward(torch.as_tensor(truth.astype(np.complex64)).to(dev), S["distances"], S["wavelength"],
+                            S["pixel"])
+    inten = (fields.abs() ** 2).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    y = torch.as_tensor(np.stack([synth.gaussian_measure(I, S["noise"], rng) for I in inten])).to(dev)
+    geo = (y, S["distances"], S["wavelength"], S["pixel"])
+
+    def fista(constraint, tau=S["tau"]):
+        return lambda k: ctv.phase_retrieval(*geo, tau=tau, gamma=S["gamma"], outer=k, inner=S["inner"],
+                                             kind=S["kind"], alpha=S["alpha"], constraint=constraint)
+
+    def rmse(run, ks=(10, 50, S["outer"])):
+        return {f"rmse_{k}": round(phase_rmse(run(k).cpu().numpy(), truth), 5) for k in ks}
+
+    return {"what": "Section VI-A's simulated setup on a synthetic pure phase object: phase RMSE (rad) of IP, TV "
+                    "and CTV (type-I anisotropic, 10 FGP iterations per prox, gamma 1) at tau 0.01 and 0.1",
+            "backprop_rmse": round(phase_rmse(ctv.phase_retrieval_ip(*geo, iters=0).cpu().numpy(), truth), 5),
+            "ip": rmse(lambda k: ctv.phase_retrieval_ip(*geo, iters=k)),
+            "tv": rmse(fista("none")), "ctv": rmse(fista("modulus")),
+            "tv_tau_0.1": rmse(fista("none", 0.1)), "ctv_tau_0.1": rmse(fista("modulus", 0.1)),
+            "ctv_rmse_100_by_tau": {str(t): rmse(fista("modulus", t), (S["outer"],))[f"rmse_{S['outer']}"]
+                                    for t in (0.003, 0.01, 0.03, 0.1, 0.3, 1.0)}}
 
 
 def phase_rmse(x, truth):

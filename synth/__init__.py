@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "piecewise_complex", "cn_noise", "square_mask", "denoise_case", "config1",
     "config2", "config3", "config4", "config5_object", "poisson_measure",
-    "PR_DEFAULTS",
+    "PR_DEFAULTS", "PR_PAPER_SIM", "phase_object", "gaussian_measure",
 ]
 
 
@@ -158,7 +158,8 @@ def _smooth_field(H, W, n_shapes, rng, sigma_px):
             hw = rng.uniform(0.03, 0.2) * W
             sel = (np.abs(jj - cj) <= hh) & (np.abs(kk - ck) <= hw)
         f[sel] = rng.uniform()
-    f = gaussian_filter(f, sigma_px, mode="wrap")
+    if sigma_px > 0:
+        f = gaussian_filter(f, sigma_px, mode="wrap")
     f = f - f.min()
     top = f.max()
     return f / (top * (1 + 1e-12)) if top > 0 else f
@@ -177,6 +178,34 @@ def config5_object(seed=0, size=1024, n_shapes=40, sigma_px=4.0):
     fa = _smooth_field(size, size, n_shapes, rng, sigma_px)
     fp = _smooth_field(size, size, n_shapes, rng, sigma_px)
     return (0.3 + 0.7 * fa) * np.exp(1j * 2.0 * fp)
+
+
+# The simulated experiment of Section VI-A: a 256 x 256 pure phase object with
+# its phase in [0, pi), pixel 5 um, wavelength 500 nm, one distance of 5 mm,
+# 10 % Gaussian noise on the intensity, type-I anisotropic TV, 10 FGP
+# iterations per prox, all methods from the back-propagated field. The paper
+# does not state tau; 0.01 here, with a sweep beside it.
+PR_PAPER_SIM = dict(wavelength=500e-9, pixel=5e-6, distances=(5e-3,), noise=0.10, size=256, outer=100,
+                    inner=10, tau=0.01, gamma=1.0, kind="1a", alpha=0.5)
+
+
+def phase_object(seed=0, size=256, n_shapes=30):
+    """Pure phase object exp(i pi f) (the stand-in for the paper's phase-only
+    test images): f a piecewise-constant random field of n_shapes shapes
+    (drawn as for config5_object, no smoothing, sharp edges) normalised to
+    [0, 1), so the phase lies in [0, pi)."""
+    rng = np.random.default_rng(seed)
+    f = _smooth_field(size, size, n_shapes, rng, 0.0)
+    return np.exp(1j * math.pi * f)
+
+
+def gaussian_measure(intensity, rel_sigma, rng):
+    """Intensity with additive white Gaussian noise whose standard deviation is
+    rel_sigma times the mean intensity (the reading of "10 % Gaussian noise");
+    float32, not clipped (the square root of the data clips at 0)."""
+    intensity = np.asarray(intensity, dtype=np.float64)
+    noise = rng.standard_normal(intensity.shape) * (rel_sigma * float(intensity.mean()))
+    return (intensity + noise).astype(np.float32)
 
 
 def poisson_measure(intensity, photons, rng):

@@ -42,3 +42,18 @@ def test_pr_object_and_poisson():
     assert ph.min() >= -1e-12 and ph.max() < 2.0
     y = synth.poisson_measure(np.full((50, 50), 2.0), 1000.0, np.random.default_rng(0))
     assert y.dtype == np.float32 and abs(y.mean() - 2.0) < 0.01
+
+
+def test_phase_object_and_gaussian_noise():
+    x = synth.phase_object(seed=3, size=96, n_shapes=8)
+    assert x.shape == (96, 96)
+    assert np.allclose(np.abs(x), 1.0)
+    ph = np.angle(x)
+    assert ph.min() >= -1e-12 and ph.max() < np.pi
+    assert len(np.unique(np.round(ph, 12))) <= 9  # piecewise constant: background + 8 shapes at most
+    assert np.array_equal(x, synth.phase_object(seed=3, size=96, n_shapes=8))
+    rng = np.random.default_rng(0)
+    I = np.full((200, 200), 2.0)
+    y = synth.gaussian_measure(I, 0.1, rng)
+    assert y.dtype == np.float32
+    assert abs(float(y.mean()) - 2.0) < 0.01 and abs(float(y.std()) - 0.2) < 0.01
