@@ -51,3 +51,48 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _summary(path, doc):
+    import json
+    with open(path, "w") as f:
+        f.write("# summary\n\n```json\n" + json.dumps(doc) + "\n```\n")
+
+
+def test_profile_figures_per_unit_and_source_gate(tmp_path, monkeypatch):
+    """The secondary roofline blocks read the committed rocprofv3 summaries:
+    launches per unit are normalised by the marker kernel, the measured rate is
+    traffic over the profiled duration, and a summary taken on other sources
+    (hash mismatch) is ignored."""
+    from paper_2109_05496_amd import prof_summary as ps
+    g = ps.GROUPS["pr"]
+    good = {"group": "pr", "sources": list(g["sources"]), "source_sha256": ps.source_hash(g["sources"])}
+    (tmp_path / "profiles").mkdir()
+    stats = dict(good, kernels={"void ctv::(anonymous namespace)::fft_acc_inverse_kernel<1024, true>(a)":
+                                {"calls": 300, "avg_us": 20.0},
+                                "void ctv::fgp_col_kernel<0, 1, false, 8, 4, false>(b)": {"calls": 900, "avg_us": 25.0},
+                                "void ctv::(anonymous namespace)::fft_line_kernel<1024, 1, false>(c)":
+                                {"calls": 300, "avg_us": 10.0}})
+    pmc = dict(good, kernels={"void ctv::(anonymous namespace)::fft_acc_inverse_kernel<1024, true>(a)":
+                              {"traffic_bytes": 80_000_000, "valu_issue_frac": 0.4},
+                              "void ctv::fgp_col_kernel<0, 1, false, 8, 4, false>(b)":
+                              {"traffic_bytes": 60_000_000, "valu_issue_frac": 0.5}})
+    _summary(tmp_path / "profiles" / "s.md", stats)
+    _summary(tmp_path / "profiles" / "p.md", pmc)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    figs = bench.profile_figures(("s.md", "p.md"), "fft_acc_inverse_kernel", ("fft_", "fgp_"))
+    acc = figs["void ctv::(anonymous namespace)::fft_acc_inverse_kernel<1024, true>(a)"]
+    fgp = figs["void ctv::fgp_col_kernel<0, 1, false, 8, 4, false>(b)"]
+    line = figs["void ctv::(anonymous namespace)::fft_line_kernel<1024, 1, false>(c)"]
+    assert acc["launches_per_unit"] == 1.0 and fgp["launches_per_unit"] == 3.0
+    assert acc["hbm"]["achieved"] == pytest.approx(80e6 / 20e-6 / 1e9, rel=1e-3)
+    assert acc["hbm"]["frac"] == pytest.approx(80e6 / 20e-6 / 1e9 / bench.HBM_PEAK_GBS, rel=1e-3)
+    assert line["traffic_bytes"] is None and "hbm" not in line
+    is_fft = lambda k: "fft_" in k  # noqa: E731
+    assert bench._per_unit(figs, is_fft, "avg_us") == pytest.approx(30.0)
+    assert bench._per_unit(figs, lambda k: True, "avg_us") == pytest.approx(105.0)
+    assert bench._per_unit(figs, is_fft, "traffic_bytes") is None  # a kernel without counters
+    assert bench._per_unit(figs, lambda k: "fgp_" in k, "traffic_bytes") == pytest.approx(180e6)
+    stale = dict(stats, source_sha256="0" * 64)
+    _summary(tmp_path / "profiles" / "s.md", stale)
+    assert bench.profile_figures(("s.md", "p.md"), "fft_acc_inverse_kernel", ("fft_",)) is None
