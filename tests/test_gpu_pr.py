@@ -234,7 +234,8 @@ def test_line_search_and_warm_start_config5():
 
 
 @pytest.mark.parametrize("m,n,D", [(64, 64, 6), (32, 32, 9), (16, 64, 3), (64, 16, 2), (128, 64, 5),
-                                   (2048, 64, 2), (64, 2048, 2), (4096, 32, 2), (32, 4096, 2)])
+                                   (2048, 64, 2), (64, 2048, 2), (4096, 32, 2), (32, 4096, 2),
+                                   (2, 2, 2), (4, 8, 3), (8, 2, 1)])
 def test_gradient_distance_counts_and_short_lines(m, n, D):
     """The gradient's last forward pass sums conj(H_d) over the distances and
     inverts the sum in one launch, up to four distances side by side: more
@@ -256,6 +257,25 @@ def test_gradient_distance_counts_and_short_lines(m, n, D):
     assert elem(g.cpu().numpy(), gref) <= ELEM_TOL, elem(g.cpu().numpy(), gref)
     lref = opr.data_term(x.astype(np.complex128), sy, Hs)
     assert abs(float(loss.cpu()[0]) - lref) <= 1e-5 * lref
+
+
+@pytest.mark.parametrize("m,n", [(2, 2), (4, 8), (8, 2), (16, 4)])
+def test_smallest_grids_one_fista_iteration(m, n):
+    """The smallest grids the entry point accepts (powers of two from 2): one
+    FISTA iteration (gradient step and FGP prox on a tile smaller than one
+    wave) against the oracle."""
+    big = synth.config5_object(seed=12, size=16, n_shapes=4, sigma_px=1.0)
+    truth = big[:m, :n]
+    dists = P5["distances"][:2]
+    Hs = [opr.transfer(m, n, d, P5["wavelength"], P5["pixel"]) for d in dists]
+    rng = np.random.default_rng(12)
+    y = np.stack([synth.poisson_measure(np.abs(opr.A(truth, H)) ** 2, P5["photons"], rng) for H in Hs])
+    xg = ctv().phase_retrieval(dev(y), dists, P5["wavelength"], P5["pixel"], tau=0.02, gamma=0.4, outer=1, inner=5,
+                               kind="1i").cpu().numpy()
+    xo, _ = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 1, 5, 0.02, 0.4, "1i")
+    print("smallest grid", m, n, "rel-L2", rel(xg, xo), "elementwise", elem(xg, xo))
+    assert rel(xg, xo) <= 1e-5, rel(xg, xo)
+    assert elem(xg, xo) <= ELEM_TOL, elem(xg, xo)
 
 
 @pytest.mark.parametrize("m,n", [(64, 128), (128, 32)])
