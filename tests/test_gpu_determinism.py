@@ -69,13 +69,19 @@ def test_backward_repeats_bitwise():
     same_every_time(lambda: ctv().denoise_backward(b, 0.05, gx, saved, iters=23, ckpt_every=5))
 
 
-def test_phase_retrieval_repeats_bitwise():
+@pytest.mark.parametrize("size,outer", [(128, 5), (1024, 2)])
+def test_phase_retrieval_repeats_bitwise(size, outer):
+    """Also at 1024^2, where the gradient runs the round-trip and
+    accumulate-inverse passes with one wave per line and four distances
+    side by side, and the iterative-projection method."""
     P = synth.PR_DEFAULTS
-    truth = synth.config5_object(seed=1, size=128, n_shapes=8)
+    truth = synth.config5_object(seed=1, size=size, n_shapes=8)
     f = ctv().pr_forward(torch.as_tensor(truth.astype(np.complex64)).cuda(), P["distances"], P["wavelength"],
                          P["pixel"])
     rng = np.random.default_rng(3)
     y = torch.as_tensor(np.stack([synth.poisson_measure(I, P["photons"], rng)
                                   for I in (f.abs() ** 2).cpu().numpy().astype(np.float64)])).cuda()
     same_every_time(lambda: ctv().phase_retrieval(y, P["distances"], P["wavelength"], P["pixel"], tau=0.01,
-                                                  gamma=0.25, outer=5, inner=10, loss=True))
+                                                  gamma=0.25, outer=outer, inner=10, loss=True))
+    same_every_time(lambda: ctv().phase_retrieval_ip(y, P["distances"], P["wavelength"], P["pixel"], iters=outer,
+                                                     loss=True))
