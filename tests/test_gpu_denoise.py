@@ -381,6 +381,30 @@ def test_empty_support_and_large_lambda():
         assert rel(x, xo) <= TOL, kind
 
 
+def test_16384_state_offsets_past_2_to_32_bytes_on_crops():
+    """A 16384^2 image (8 GiB of dual state: byte offsets into one state plane
+    reach 2^32, into the state 2^33): masked type-1i windows across the
+    support's top-left and bottom-right corners and inside it, and the same
+    image without a support (type-2a) on two opposite image corners, K = 16."""
+    c = synth.config2(0, size=16384, n_shapes=40)
+    b, mask, K = c["b"], c["mask"], 16
+    m, n = b.shape
+    S = 160
+    rows = np.flatnonzero(mask.any(axis=1))
+    cols = np.flatnonzero(mask.any(axis=0))
+    r_top, r_bot, c_left, c_right = int(rows[0]), int(rows[-1]), int(cols[0]), int(cols[-1])
+    clip = lambda v, hi: int(min(max(v, 0), hi - S))  # noqa: E731
+    windows = ((clip(r_top - S // 2, m), clip(c_left - S // 2, n)),
+               (clip(r_bot - S // 2, m), clip(c_right - S // 2, n)),
+               (clip((r_top + r_bot) // 2, m), clip((c_left + c_right) // 2, n)))
+    bt, mt = dev(b), dev(mask)
+    x = ctv().denoise(bt, c["lam"], kind="1i", alpha=c["alpha"], support=mt, iters=K).cpu().numpy()
+    _check_crops(x, b, mask, c["lam"], K, "1i", c["alpha"], S, windows, "16384 masked")
+    del x
+    x = ctv().denoise(bt, c["lam"], kind="2a", alpha=c["alpha"], iters=K).cpu().numpy()
+    _check_crops(x, b, None, c["lam"], K, "2a", c["alpha"], S, ((0, 0), (m - S, n - S)), "16384 unmasked")
+
+
 def test_8192_full_size_against_oracle_on_crops():
     """The out-of-cache benchmark size (masked 8192^2, K = 48; 2 GiB of dual
     state, so every state offset is past 2^31 bytes): windows across the
