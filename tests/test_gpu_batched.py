@@ -119,3 +119,30 @@ def test_batched_gradient_projection_method():
         assert rel(x, xo) <= 1e-5, (i, rel(x, xo))
         assert elem(x, xo) <= ELEM_TOL, (i, elem(x, xo))
     plan.close()
+
+
+def test_packed_offsets_past_2_to_31_bytes():
+    """A plan whose first image is 8192^2 (with a support, 2 GiB of dual state)
+    and whose later images therefore start past 2^31 bytes into the packed
+    state and past 2^28 elements into the packed inputs: every image equals
+    the plain call bit for bit (the plain path is checked against the oracle
+    at 8192^2 and 16384^2 on crops)."""
+    rng = np.random.default_rng(7)
+    c = synth.config2(0, size=8192, n_shapes=40)
+    big_b = c["b"]
+    big_mask = c["mask"]
+    small = [(300, 500, "1a", 0.05, 12), (1000, 64, "2i", 0.1, 16), (65, 129, "1i", 0.08, 9)]
+    imgs = [dict(m=8192, n=8192, lam=c["lam"], kind="1i", alpha=0.5, iters=16, has_support=True)]
+    bs, masks = [big_b], [big_mask]
+    for m, n, kind, lam, K in small:
+        _, b = synth.denoise_case(m, n, 5, 0.15, rng)
+        imgs.append(dict(m=m, n=n, lam=lam, kind=kind, alpha=0.3 if kind[0] == "2" else 0.5, iters=K,
+                         has_support=False))
+        bs.append((b * 1.5).astype(np.complex64))
+    plan = ctv().BatchedPlan(imgs)
+    out = plan.unpack(plan.run(plan.pack(bs), plan.pack_support(masks)))
+    torch.cuda.synchronize()
+    for i, (d, b) in enumerate(zip(imgs, bs)):
+        ref = plain(b, d, big_mask if i == 0 else None)
+        assert torch.equal(out[i].reshape(d["m"], d["n"]), ref), i
+    plan.close()
