@@ -66,6 +66,41 @@ def test_backward_matches_oracle_reverse(kind, constraint, shape, K):
     assert abs(gl[0] - glo) <= TOL * max(1.0, abs(glo)), (gl[0], glo)
 
 
+def test_backward_8192_local_cotangent_against_oracle_on_a_crop():
+    """Masked 8192^2, type-1i, K = 10 with checkpoints every 5 (1 GiB per dual
+    plane; the recomputed r history 5 GiB): a cotangent nonzero only on a
+    48 x 48 window inside the support near its bottom-right corner. x there
+    depends on b within distance K + 1 only, so grad_b must vanish exactly
+    outside a crop with a margin of 2 (K + 2) around the window, and the
+    oracle's reverse pass on that crop gives grad_b and grad_lambda (the
+    iterates it needs lie at least K + 2 from the crop's cut edges)."""
+    c = synth.config2(0, size=8192, n_shapes=40)
+    b, mask = c["b"], c["mask"]
+    m, n = b.shape
+    K, ck, lam = 10, 5, c["lam"]
+    rows = np.flatnonzero(mask.any(axis=1))
+    cols = np.flatnonzero(mask.any(axis=0))
+    W = 48
+    r0, c0 = int(rows[-1]) - 100, int(cols[-1]) - 100
+    rng = np.random.default_rng(21)
+    xbar = np.zeros((m, n), dtype=np.complex64)
+    xbar[r0:r0 + W, c0:c0 + W] = (rng.standard_normal((W, W)) + 1j * rng.standard_normal((W, W))).astype(np.complex64)
+    _, gb, gl = gpu_vjp(b, lam, K, xbar, "1i", 0.5, "modulus", mask, ckpt=ck)
+    M = 2 * (K + 2)
+    R0, R1, C0, C1 = max(r0 - M, 0), min(r0 + W + M, m), max(c0 - M, 0), min(c0 + W + M, n)
+    outside = np.ones((m, n), dtype=bool)
+    outside[R0:R1, C0:C1] = False
+    assert not np.any(gb[0][outside]), "grad_b nonzero beyond the cotangent's dependency cone"
+    _, gbo, glo = oadj.fgp_vjp(b[R0:R1, C0:C1].astype(np.complex128), lam, K,
+                               xbar[R0:R1, C0:C1].astype(np.complex128), "1i", 0.5, "modulus",
+                               mask[R0:R1, C0:C1])
+    got = gb[0][R0:R1, C0:C1]
+    print("adjoint 8192 crop grad_b rel-L2", rel(got, gbo), "elementwise", elem(got, gbo),
+          "grad_lambda rel", abs(gl[0] - glo) / max(1.0, abs(glo)))
+    assert rel(got, gbo) <= TOL
+    assert abs(gl[0] - glo) <= TOL * max(1.0, abs(glo)), (gl[0], glo)
+
+
 @pytest.mark.parametrize("kind", tv.KINDS)
 def test_backward_with_mask(kind):
     rng = np.random.default_rng(9)
