@@ -259,6 +259,28 @@ def test_gradient_distance_counts_and_short_lines(m, n, D):
     assert abs(float(loss.cpu()[0]) - lref) <= 1e-5 * lref
 
 
+def test_gradient_at_the_largest_grid():
+    """4096 x 4096, the largest grid the entry points accept, two distances:
+    A_d x, the gradient and the data term against the oracle (the 4096-point
+    round trip holds two columns per block, one block per CU)."""
+    m = 4096
+    truth = synth.config5_object(seed=13, size=m, n_shapes=20, sigma_px=4.0)
+    dists = P5["distances"][:2]
+    Hs = [opr.transfer(m, m, d, P5["wavelength"], P5["pixel"]) for d in dists]
+    rng = np.random.default_rng(13)
+    y = np.stack([synth.poisson_measure(np.abs(opr.A(truth, H)) ** 2, P5["photons"], rng) for H in Hs])
+    x = (truth * np.exp(0.2j) + 0.05).astype(np.complex64)
+    g, loss = ctv().pr_gradient(dev(x), dev(y), dists, P5["wavelength"], P5["pixel"])
+    sy = [np.sqrt(np.maximum(yy.astype(np.float64), 0)) for yy in y]
+    gref = opr.grad_F(x.astype(np.complex128), sy, Hs)
+    g = g.cpu().numpy()
+    print("gradient 4096^2 rel-L2", rel(g, gref), "elementwise", elem(g, gref))
+    assert rel(g, gref) <= 1e-5
+    assert elem(g, gref) <= ELEM_TOL, elem(g, gref)
+    lref = opr.data_term(x.astype(np.complex128), sy, Hs)
+    assert abs(float(loss.cpu()[0]) - lref) <= 1e-5 * lref
+
+
 @pytest.mark.parametrize("m,n", [(2, 2), (4, 8), (8, 2), (16, 4)])
 def test_smallest_grids_one_fista_iteration(m, n):
     """The smallest grids the entry point accepts (powers of two from 2): one
