@@ -99,9 +99,10 @@ std::vector<Candidate> candidates(bool batched, int iters, bool single_tile) {
     int waves, rows, tmax;
   };
   // (kSweepShape, SH): the row-sweep tile with segments of SH output rows
-  static const Shape plain_shapes[] = {{8, 8, 12}, {8, 4, 8}, {4, 8, 8}, {16, 4, 10},
+  static const Shape plain_shapes[] = {{8, 8, 12}, {8, 4, 8}, {4, 8, 8}, {12, 4, 10}, {16, 4, 10},
                                        {kSweepShape, 144, kSweepMaxFuse}};
-  static const Shape batched_shapes[] = {{8, 8, 12}, {8, 4, 8}, {16, 4, 10}, {kSweepShape, 144, kSweepMaxFuse}};
+  static const Shape batched_shapes[] = {{8, 8, 12}, {8, 4, 8}, {12, 4, 10}, {16, 4, 10},
+                                         {kSweepShape, 144, kSweepMaxFuse}};
   std::vector<Candidate> out;
   const int kcap = std::max(1, iters);
   auto add_shape = [&](const Shape& s) {

@@ -93,7 +93,8 @@ bool valid_tile_shape(const TileShape& ts) {
   if (ts.sweep()) return ts.rows_per_thread >= 16 && ts.rows_per_thread <= 1024 && ts.rows_per_thread % 4 == 0;
   if (ts.waves > 0)
     return (ts.waves == 4 && ts.rows_per_thread == 8) ||
-           ((ts.waves == 8 || ts.waves == 16) && (ts.rows_per_thread == 4 || ts.rows_per_thread == 8));
+           ((ts.waves == 8 || ts.waves == 16) && (ts.rows_per_thread == 4 || ts.rows_per_thread == 8)) ||
+           (ts.waves == 12 && ts.rows_per_thread == 4);
   return ts.rows_per_thread == 4 || ts.rows_per_thread == 8 || ts.rows_per_thread == 16;
 }
 

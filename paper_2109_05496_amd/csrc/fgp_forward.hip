@@ -932,6 +932,7 @@ static hipError_t launch_col_shape(const FgpPlainArgs& a, int nw, int p, int nb,
   CTV_COL(4, 8)
   CTV_COL(8, 4)
   CTV_COL(8, 8)
+  CTV_COL(12, 4)
   CTV_COL(16, 4)
   CTV_COL(16, 8)
 #undef CTV_COL
@@ -1038,6 +1039,7 @@ const void* fgp_batched_kernel_ptr(int constr, const TileShape& ts) {
                            : reinterpret_cast<const void*>(&fgp_batched_kernel<C_NONE, NW_, P_>);
   CTV_BK(8, 8)
   CTV_BK(8, 4)
+  CTV_BK(12, 4)
   CTV_BK(16, 4)
 #undef CTV_BK
   return nullptr;

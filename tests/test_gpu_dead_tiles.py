@@ -51,7 +51,7 @@ def zero_state(B, m, n):
     return torch.zeros((B, 2, m, n, 4), dtype=torch.float32, device="cuda")
 
 
-SHAPES = [(8, 8), (8, 4), (4, 8), (16, 4), (16, 8)]
+SHAPES = [(8, 8), (8, 4), (4, 8), (12, 4), (16, 4), (16, 8)]
 
 
 @pytest.mark.parametrize("kind", tv.KINDS)
@@ -214,7 +214,7 @@ def test_random_supports_plain_and_batched():
     kinds, tile shapes, fusion depths and K): plain calls equal their every-tile
     runs, and one batched plan of all of them equals the plain calls."""
     rng = np.random.default_rng(47)
-    shapes = [(8, 8), (8, 4), (4, 8), (16, 4), (16, 8)]
+    shapes = [(8, 8), (8, 4), (4, 8), (12, 4), (16, 4), (16, 8)]
     imgs, bs, masks, outs = [], [], [], []
     for case in range(20):
         m, n = int(rng.integers(1, 301)), int(rng.integers(1, 301))

@@ -170,7 +170,7 @@ def test_duality_gap_matches_oracle(kind):
     assert abs(gpu_gap - ora) <= bound + 1e-12 * abs(ora), (gpu_gap, ora, bound)
 
 
-SHAPES = [(-1, 4), (-1, 8), (-1, 16), (4, 8), (8, 4), (8, 8), (16, 4), (16, 8)]
+SHAPES = [(-1, 4), (-1, 8), (-1, 16), (4, 8), (8, 4), (8, 8), (12, 4), (16, 4), (16, 8)]
 
 
 @pytest.mark.parametrize("kind", tv.KINDS)
