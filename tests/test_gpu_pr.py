@@ -259,6 +259,28 @@ def test_gradient_distance_counts_and_short_lines(m, n, D):
     assert abs(float(loss.cpu()[0]) - lref) <= 1e-5 * lref
 
 
+def test_degenerate_iteration_counts():
+    """Zero outer iterations return the back-propagated field (or x_0 exactly);
+    a prox of zero FGP iterations is P_C alone, and so is one of tau = 0; both
+    against the oracle's Algorithm 1 with the same counts."""
+    truth, Hs, y = small_problem(m=128, D=3)
+    dists = P5["distances"][:3]
+    sy = [np.sqrt(np.maximum(yy.astype(np.float64), 0)) for yy in y]
+    geo = (dev(y), dists, P5["wavelength"], P5["pixel"])
+    x0 = ctv().phase_retrieval(*geo, tau=0.02, gamma=0.4, outer=0, inner=5).cpu().numpy()
+    ref0 = opr.backprop(sy, Hs)
+    assert rel(x0, ref0) <= 1e-5 and elem(x0, ref0) <= ELEM_TOL
+    start = (truth * np.exp(0.3j)).astype(np.complex64)
+    same = ctv().phase_retrieval(*geo, tau=0.02, gamma=0.4, outer=0, inner=5, x0=dev(start)).cpu().numpy()
+    assert np.array_equal(same, start)
+    for tau, inner in ((0.02, 0), (0.0, 5)):
+        xg = ctv().phase_retrieval(*geo, tau=tau, gamma=0.4, outer=3, inner=inner).cpu().numpy()
+        xo, _ = opr.fista(y.astype(np.float64), dists, P5["wavelength"], P5["pixel"], 3, inner, tau, 0.4, "1i")
+        print("degenerate tau", tau, "inner", inner, "rel-L2", rel(xg, xo), "elementwise", elem(xg, xo))
+        assert rel(xg, xo) <= 1e-5 and elem(xg, xo) <= ELEM_TOL, (tau, inner)
+        assert np.abs(xg).max() <= 1.0 + 1e-6
+
+
 def test_gradient_at_the_largest_grid():
     """4096 x 4096, the largest grid the entry points accept, two distances:
     A_d x, the gradient and the data term against the oracle (the 4096-point
