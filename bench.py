@@ -21,8 +21,8 @@ The fused kernel performs several iterations per launch, so its real memory
 traffic is far below the per-iteration algorithmic bytes: it is bound by VALU
 issue. `roofline` reports the algorithmic FP32 FLOP/s (FMA = 2) against the
 published 157.3 TFLOP/s vector peak; as secondary fields the algorithmic
-operations per second against the VALU issue peak of this build (no packed
-FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), the measured HBM traffic of the
+operations per second against the VALU issue peak of the library's code (it is
+compiled without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), the measured HBM traffic of the
 committed PMC profile per second against the 8 TB/s peak (the metric's "%HBM",
 when the kernel sources are unchanged since the profile was taken) and the
 bytes an unfused solver would move (57 B per pixel-iteration), whose ratio to
@@ -39,9 +39,9 @@ import time
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# VALU issue peak without packed FP32 (this build disables packed-FP32 code
-# generation): 256 CUs x 4 SIMDs x 16 lanes, one operation per lane per cycle
-# at 2.4 GHz.
+# VALU issue peak without packed FP32 (the library is compiled with packed-FP32
+# code generation disabled): 256 CUs x 4 SIMDs x 16 lanes, one operation per
+# lane per cycle at 2.4 GHz.
 VALU_OPS_PEAK_GOPS = 256 * 4 * 16 * 2.4
 BYTES_PER_PX_IT_MASKED = 57    # read b 8 + q 16 + r 16 + mask 1, write q 16 (per pixel-iteration)
 FLOPS_PER_PX_IT = {"1i": 52, "1a": 52, "2i": 52, "2a": 44}
@@ -381,8 +381,9 @@ def bench_adjoint(ctv, synth, torch, dev, reps=3):
     kern_us = _per_unit(figs, lambda k: True, "avg_us") if figs else None
     step_k = next((k for k in figs if "adj_step_kernel" in k), None) if figs else None
     sk = figs[step_k] if step_k else None
-    # SURVEY prices the backward against HBM; the profiles say which unit of the
-    # dominant (reverse-step) kernel is busier: VALU issue or HBM
+    # the block prices the backward against HBM (its unfused byte model); the
+    # profiles say which unit of the dominant (reverse-step) kernel is busier:
+    # VALU issue or HBM
     limiter = None
     if sk and sk.get("valu_issue_frac") is not None and sk.get("hbm"):
         limiter = {"valu_issue_frac": sk["valu_issue_frac"], "hbm_frac": sk["hbm"]["frac"],
@@ -702,7 +703,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(this build runs on a single MI355X; multi-GPU sharding is design-only)", file=sys.stderr)
+              "(the library runs on one MI355X; multi-GPU sharding is design-only)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -798,7 +799,7 @@ def main():
             "flops_per_px_it": {k: FLOPS_PER_PX_IT[k] for k in kinds},
             "live_tiles": [len(kinds) * live_tiles, len(kinds) * all_tiles],
             "computed_px_frac": round(live_px / (m * n), 4),
-            # the same work against the VALU issue rate of this build (non-packed FP32:
+            # the same work against the VALU issue rate of the library's code (non-packed FP32:
             # one lane-operation per lane per cycle), counting an FMA, a min, a max or
             # a reciprocal square root as one operation
             "valu_issue": {"achieved": round(achieved_gops, 1), "peak": round(VALU_OPS_PEAK_GOPS, 1), "unit": "Gop/s",
