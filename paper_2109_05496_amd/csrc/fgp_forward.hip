@@ -191,25 +191,52 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
   const long long plane = (long long)J.m * J.n;
   const float2 zero2 = make_float2(0.0f, 0.0f);
 
+  // Offset of the region's row i at column c0: the same for every lane of the
+  // wave, so each access below is a scalar row base plus the lane's offset
+  // (no per-lane 64-bit address arithmetic).
+  auto row_off = [&](int i) { return (long long)(jb + i) * J.n + c0; };
   float4 q[P], r[P];
   float2 b[P];
   bool inside[P];
+  if (!BORDER) {
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const int j = jb + i;
-    const bool in = kin && (!BORDER || (j >= 0 && j < J.m));
-    q[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    r[i] = q[i];
-    b[i] = zero2;
-    inside[i] = !BORDER;
-    if (in) {
-      const long long p = (long long)j * J.n + k;
-      b[i] = J.b[p];
-      if (J.st_in) {
-        q[i] = ld_state<COH>(J.st_in + p);
-        r[i] = ld_state<COH>(J.st_in + plane + p);
+    for (int i = 0; i < P; ++i) {
+      const long long o = row_off(i);
+      b[i] = (J.b + o)[lane];
+      inside[i] = MASK ? ((J.mask + o)[lane] != 0) : true;
+    }
+    if (J.st_in) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const long long o = row_off(i);
+        q[i] = ld_state<COH>(J.st_in + o + lane);
+        r[i] = ld_state<COH>(J.st_in + plane + o + lane);
       }
-      inside[i] = MASK ? (J.mask[p] != 0) : true;
+    } else {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        q[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r[i] = q[i];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const int j = jb + i;
+      const bool in = kin && j >= 0 && j < J.m;
+      q[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      r[i] = q[i];
+      b[i] = zero2;
+      inside[i] = false;
+      if (in) {
+        const long long o = row_off(i);
+        b[i] = (J.b + o)[lane];
+        if (J.st_in) {
+          q[i] = ld_state<COH>(J.st_in + o + lane);
+          r[i] = ld_state<COH>(J.st_in + plane + o + lane);
+        }
+        inside[i] = MASK ? ((J.mask + o)[lane] != 0) : true;
+      }
     }
   }
 
@@ -268,7 +295,7 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
         const int j = jb + i;
         const int ry = wave * P + i;
         if (col_out && ry >= H && ry < RH - H && (!BORDER || j < J.m))
-          J.r_hist[it * J.hist_stride + (long long)j * J.n + k] = r[i];
+          (J.r_hist + (it * J.hist_stride + row_off(i)))[lane] = r[i];
       }
     }
   }
@@ -291,7 +318,7 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
           left = has_left ? left : zero2;
         }
         const float2 xv = proj_c<CONSTR>(dual_to_primal(b[i], q[i], up, left, J.lam), inside[i]);
-        if (col_out && (!BORDER || j < J.m)) store_nt(J.x + (long long)j * J.n + k, xv);
+        if (col_out && (!BORDER || j < J.m)) store_nt(J.x + row_off(i) + lane, xv);
       }
     }
   }
@@ -301,9 +328,9 @@ __device__ __forceinline__ void fgp_tile_col(const TileJob& J, const int H, cons
       const int j = jb + i;
       const int ry = wave * P + i;
       if (col_out && ry >= H && ry < RH - H && (!BORDER || j < J.m)) {
-        const long long p = (long long)j * J.n + k;
-        st_state<COH>(J.st_out + p, q[i]);
-        st_state<COH>(J.st_out + plane + p, r[i]);
+        const long long o = row_off(i);
+        st_state<COH>(J.st_out + o + lane, q[i]);
+        st_state<COH>(J.st_out + plane + o + lane, r[i]);
       }
     }
   }
