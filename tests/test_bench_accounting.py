@@ -96,3 +96,22 @@ def test_profile_figures_per_unit_and_source_gate(tmp_path, monkeypatch):
     stale = dict(stats, source_sha256="0" * 64)
     _summary(tmp_path / "profiles" / "s.md", stale)
     assert bench.profile_figures(("s.md", "p.md"), "fft_acc_inverse_kernel", ("fft_",)) is None
+
+
+def test_committed_profiles_were_taken_on_the_committed_sources():
+    """Every summary under profiles/ that carries a JSON block names its kernel
+    group and the SHA-256 of that group's sources; it must be the hash of the
+    sources in the tree, or bench.py would ignore the summary (and its numbers
+    would describe other code)."""
+    from paper_2109_05496_amd import prof_summary as ps
+    prof = os.path.join(ROOT, "profiles")
+    checked = 0
+    for name in sorted(os.listdir(prof)):
+        text = open(os.path.join(prof, name)).read()
+        if "```json" not in text:
+            continue
+        doc = ps.load_summary(os.path.join(prof, name))
+        assert doc is not None, f"{name}: taken on other sources than the ones in the tree"
+        assert doc["group"] in ps.GROUPS
+        checked += 1
+    assert checked >= 8
