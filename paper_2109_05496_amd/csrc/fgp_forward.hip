@@ -673,7 +673,7 @@ constexpr int kScanWaves = 4;
 // Tile t of one image's tiling (halo, rows, tiles_x): returns whether it is
 // live (the same value in every thread). st0 / st1 / x are image bases with
 // `batch` images of stride 2 m n float4 / m n float2 (zeroed as described).
-__device__ bool scan_tile(const uint8_t* __restrict__ mask, int m, int n, int halo, int rows, int tiles_x, int t,
+__device__ __forceinline__ bool scan_tile(const uint8_t* __restrict__ mask, int m, int n, int halo, int rows, int tiles_x, int t,
                           bool zero_st, float* st0, float* st1, float* x, int batch, int* sLive) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ty = t / tiles_x, tx = t - ty * tiles_x;
@@ -687,25 +687,44 @@ __device__ bool scan_tile(const uint8_t* __restrict__ mask, int m, int n, int ha
   const int jlo = j0 + wave * band, jhi = min(jend, jlo + band);
   bool below = (kin && jhi < m && jhi > jlo) ? (mask[(long long)jhi * n + k] != 0) : false;
   bool live = false;
-  for (int j = jhi - 1; j >= jlo; --j) {
-    const long long p = (long long)j * n + k;
-    const bool cur = kin ? (mask[p] != 0) : false;
-    const bool right = __shfl_down(cur ? 1 : 0, 1) != 0 && lane < 63;
-    const bool dead = !cur && !below && !right;
-    if (kout) {
-      live = live || !dead;
-      if (zero_st && dead) {
-        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int img = 0; img < batch; ++img) {
-          const long long base = (long long)img * 2 * px;
-          reinterpret_cast<float4*>(st0)[base + p] = z;
-          reinterpret_cast<float4*>(st0)[base + px + p] = z;
-          reinterpret_cast<float4*>(st1)[base + p] = z;
-          reinterpret_cast<float4*>(st1)[base + px + p] = z;
+  // Rows in chunks of kChunk, bottom up: every support byte of a chunk is
+  // loaded before the first is tested (the zero stores in between would
+  // otherwise order each load after the previous row's stores).
+  constexpr int kChunk = 16;
+  for (int top = jhi; top > jlo; top -= kChunk) {
+    const int cnt = min(kChunk, top - jlo);  // rows top - 1, ..., top - cnt
+    // unconditional loads from a clamped, valid position (a load in a branch of
+    // its own waits for the one before it); the bytes that do not belong to
+    // the band are zeroed afterwards
+    const int kc = min(k, n - 1);
+    int mb[kChunk];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) mb[i] = mask[(long long)max(top - 1 - i, 0) * n + kc];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) mb[i] = (kin && i < cnt) ? mb[i] : 0;
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) {
+      if (i < cnt) {  // uniform over the wave
+        const long long p = (long long)(top - 1 - i) * n + k;
+        const bool cur = mb[i] != 0;
+        const bool right = __shfl_down(cur ? 1 : 0, 1) != 0 && lane < 63;
+        const bool dead = !cur && !below && !right;
+        if (kout) {
+          live = live || !dead;
+          if (zero_st && dead) {
+            const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int img = 0; img < batch; ++img) {
+              const long long base = (long long)img * 2 * px;
+              reinterpret_cast<float4*>(st0)[base + p] = z;
+              reinterpret_cast<float4*>(st0)[base + px + p] = z;
+              reinterpret_cast<float4*>(st1)[base + p] = z;
+              reinterpret_cast<float4*>(st1)[base + px + p] = z;
+            }
+          }
         }
+        below = cur;
       }
     }
-    below = cur;
   }
   const bool wave_live = __builtin_amdgcn_ballot_w64(live) != 0;
   if (lane == 0) sLive[wave] = wave_live ? 1 : 0;
