@@ -266,53 +266,57 @@ __device__ __forceinline__ void pass_lds(const float2* L, float2 (&v)[16], int j
   dft<R, DIR>(v);
 }
 
-// The FFT of one line from the first radix-16 pass on, the thread's 16 inputs
-// (line positions lt + r * N/16) already in v, twiddles from the LDS half
-// table twh (visible after the first barrier here); the 16 outputs of the last
-// pass are returned in o[] with their positions within the line in pos[].
+// The FFT of one line from the first radix-E pass on (E = 16 or 8 elements per
+// thread), the thread's E inputs (line positions lt + r * N/E) already in v,
+// twiddles from the LDS half table twh (visible after the first barrier here);
+// the E outputs of the last pass are returned in o[] with their positions
+// within the line in pos[]. E = 8 gives a line twice the threads (for passes
+// over a single image, which otherwise leave each CU a handful of waves).
 // OPAQUE_LANE: take the lane index through an empty asm, so that a second
 // transform in the same kernel recomputes its LDS and twiddle offsets instead
 // of keeping the first one's alive in registers.
-template <int N, int DIR, bool OPAQUE_LANE = false>
+template <int N, int DIR, bool OPAQUE_LANE = false, int E = 16>
 __device__ __forceinline__ void line_fft_regs(float2* sl, const float2* twh, float2 (&v)[16], float2 (&o)[16],
                                               int (&pos)[16]) {
-  constexpr int TPL = N / 16;                  // threads per line
+  static_assert(E == 16 || E == 8, "16 or 8 elements per thread");
+  constexpr int TPL = N / E;                   // threads per line
   constexpr int L = (N == 32) ? 5 : (N == 64) ? 6 : (N == 128) ? 7 : (N == 256) ? 8 : (N == 512) ? 9
                   : (N == 1024) ? 10 : (N == 2048) ? 11 : 12;
-  constexpr int P16 = L / 4;                   // radix-16 passes
-  constexpr int RR = 1 << (L % 4);             // remainder radix (1 = none)
-  constexpr int NPASS = P16 + (RR > 1 ? 1 : 0);  // >= 2 for N >= 32
+  constexpr int LE = E == 16 ? 4 : 3;          // log2(E)
+  constexpr int PE = L / LE;                   // radix-E passes
+  constexpr int RR = 1 << (L % LE);            // remainder radix (1 = none)
+  constexpr int NPASS = PE + (RR > 1 ? 1 : 0);  // >= 2 for N >= 32
   int lt = threadIdx.x % TPL;
   if (OPAQUE_LANE) asm volatile("" : "+v"(lt));
-  dft<16, DIR>(v);
-  int Ns = 16;
+  dft<E, DIR>(v);
+  int Ns = E;
   __syncthreads();  // the previous use of this LDS line (an earlier image) is finished
 #pragma unroll
-  for (int r = 0; r < 16; ++r) sl[pidx(lt * 16 + r)] = v[r];
+  for (int r = 0; r < E; ++r) sl[pidx(lt * E + r)] = v[r];
   __syncthreads();
 #pragma unroll
   for (int p = 1; p < NPASS; ++p) {
     const bool last = (p == NPASS - 1);
-    if (p < P16) {
-      pass_lds<N, 16, DIR, TPL>(sl, v, lt, Ns, twh);
+    if (p < PE) {
+      pass_lds<N, E, DIR, TPL>(sl, v, lt, Ns, twh);
       const int k = lt & (Ns - 1);
-      const int d = (lt - k) * 16 + k;
+      const int d = (lt - k) * E + k;
       if (!last) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) sl[pidx(d + r * Ns)] = v[r];
+        for (int r = 0; r < E; ++r) sl[pidx(d + r * Ns)] = v[r];
         __syncthreads();
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < E; ++r) {
           o[r] = v[r];
           pos[r] = d + r * Ns;
         }
       }
-      Ns *= 16;
+      Ns *= E;
     } else {
-      // remainder pass of radix RR (always the last): 16/RR butterflies per thread
-      constexpr int B = 16 / RR;
+      // remainder pass of radix RR (always the last): E/RR butterflies per thread
+      constexpr int B = E / RR;
 #pragma unroll
       for (int bb = 0; bb < B; ++bb) {
         float2 w[16];
@@ -333,30 +337,30 @@ __device__ __forceinline__ void line_fft_regs(float2* sl, const float2* twh, flo
 
 // The 16 inputs of this thread's first pass for line `line` of image `img`
 // (positions lt + r * N/16), with the pre-operation of a.pre; zeros if !live.
-template <int N>
+template <int N, int E = 16>
 __device__ __forceinline__ void line_load(const FftArgs& a, int img, long long line, bool live, float2 (&v)[16]) {
-  constexpr int TPL = N / 16;
+  constexpr int TPL = N / E;
   const int lt = threadIdx.x % TPL;
   if (live) {
-    load_pre<16, TPL>(a, img, line * N + lt, v);
+    load_pre<E, TPL>(a, img, line * N + lt, v);
   } else {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
+    for (int r = 0; r < E; ++r) v[r] = make_float2(0.0f, 0.0f);
   }
 }
 
 // The same inputs from a line staged in LDS (natural order, pidx positions).
-template <int N>
+template <int N, int E = 16>
 __device__ __forceinline__ void line_from_lds(const float2* sl, float2 (&v)[16]) {
-  constexpr int TPL = N / 16;
+  constexpr int TPL = N / E;
   const int lt = threadIdx.x % TPL;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = sl[pidx(lt + r * TPL)];
+  for (int r = 0; r < E; ++r) v[r] = sl[pidx(lt + r * TPL)];
 }
 
-template <int N, int DIR, bool ACCALL>
+template <int N, int DIR, bool ACCALL, int E = 16>
 __global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
-  constexpr int TPL = N / 16;
+  constexpr int TPL = N / E;
   constexpr int LPB = kThreads / TPL;          // lines per block
   constexpr int LS = N + N / 16;               // padded LDS line length
   __shared__ float2 s[LPB * LS];
@@ -371,6 +375,7 @@ __global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
   TwStage<N, kThreads> tws;
   tws.fetch(a.tw);
   if (ACCALL) {
+    static_assert(!ACCALL || E == 16, "the accumulate-all pass runs 16 elements per thread");
     // acc (+)= sum over the n_acc images of conj(H_img) * FFT(line of image img)
     float2 sum[16];
 #pragma unroll
@@ -397,11 +402,11 @@ __global__ __launch_bounds__(kThreads) void fft_line_kernel(FftArgs a) {
     return;
   }
   const int img = blockIdx.y;
-  line_load<N>(a, img, line, live, v);
+  line_load<N, E>(a, img, line, live, v);
   tws.store(twh);
-  line_fft_regs<N, DIR>(sl, twh, v, o, pos);
+  line_fft_regs<N, DIR, false, E>(sl, twh, v, o, pos);
   double loss = 0.0;
-  if (live) post_block<16>(a, img, line * N, pos, o, loss);
+  if (live) post_block<E>(a, img, line * N, pos, o, loss);
   if (a.post == kPostResidual) {
     const double tot = block_sum(loss, red);
     if (threadIdx.x == 0) a.partial[(long long)img * gridDim.x + blockIdx.x] = tot;
@@ -552,9 +557,9 @@ constexpr int col_block() { return (512 / (N / 16)) < 8 ? (512 / (N / 16)) : 8; 
 // stages zeros, so that no load sits in a branch of its own (which would make
 // each wait for the previous one). Offsets within an image are 32-bit (the
 // launchers check N * W < 2^31), one register per address.
-template <int N, int CB, int NT, int LS>
+template <int N, int CB, int NT, int LS, int E = 16>
 __device__ __forceinline__ void stage_columns(const float2* __restrict__ in, int W, int grp, float2* s) {
-  static_assert(N * CB == 16 * NT && NT % CB == 0, "16 elements per thread, one column per thread");
+  static_assert(N * CB == E * NT && NT % CB == 0, "E elements per thread, one column per thread");
   constexpr int RSTEP = NT / CB;  // rows between a thread's consecutive elements
   const int c = threadIdx.x % CB, row0 = threadIdx.x / CB;
   const int gc = grp * CB + c;
@@ -562,12 +567,12 @@ __device__ __forceinline__ void stage_columns(const float2* __restrict__ in, int
   const int base = row0 * W + (in_range ? gc : W - 1);
   float2 v[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = in[base + k * RSTEP * W];
+  for (int k = 0; k < E; ++k) v[k] = in[base + k * RSTEP * W];
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
+  for (int k = 0; k < E; ++k)
     if (!in_range) v[k] = make_float2(0.0f, 0.0f);
 #pragma unroll
-  for (int k = 0; k < 16; ++k) s[c * LS + pidx(row0 + k * RSTEP)] = v[k];
+  for (int k = 0; k < E; ++k) s[c * LS + pidx(row0 + k * RSTEP)] = v[k];
   __syncthreads();
 }
 
@@ -588,9 +593,9 @@ __device__ __forceinline__ void unstage_columns(const float2* s, int W, int grp,
   }
 }
 
-template <int N, int DIR, int CB>
-__global__ __launch_bounds__(CB * (N / 16)) void fft_col_kernel(FftArgs a) {
-  constexpr int TPL = N / 16;
+template <int N, int DIR, int CB, int E = 16>
+__global__ __launch_bounds__(CB * (N / E)) void fft_col_kernel(FftArgs a) {
+  constexpr int TPL = N / E;
   constexpr int NT = CB * TPL;
   // padded line: with a pitch of 4 (mod 32) elements beyond the pidx length the
   // column-staging accesses (CB columns x consecutive rows per wave) measured the
@@ -608,14 +613,14 @@ __global__ __launch_bounds__(CB * (N / 16)) void fft_col_kernel(FftArgs a) {
   const int img = blockIdx.y;
   TwStage<N, NT> tws;
   tws.fetch(a.tw);
-  stage_columns<N, CB, NT, LS>(a.in + (long long)img * a.in_stride, (int)W, grp, s);
+  stage_columns<N, CB, NT, LS, E>(a.in + (long long)img * a.in_stride, (int)W, grp, s);
   tws.store(twh);
   float2 o[16], v[16];
   int pos[16];
-  line_from_lds<N>(sl, v);
-  line_fft_regs<N, DIR>(sl, twh, v, o, pos);
+  line_from_lds<N, E>(sl, v);
+  line_fft_regs<N, DIR, false, E>(sl, twh, v, o, pos);
   double loss = 0.0;
-  if (live) post_block<16>(a, img, col * N, pos, o, loss);
+  if (live) post_block<E>(a, img, col * N, pos, o, loss);
   if (a.post == kPostResidual) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) loss += __shfl_xor(loss, off, 64);
@@ -846,6 +851,12 @@ __global__ __launch_bounds__(256) void copy_c_kernel(const float2* __restrict__ 
   if (p < total) b[p] = a[p];
 }
 
+// A pass of `lines` N-point lines (all images) gives fewer than 8 waves per
+// CU at 16 elements per thread: run it at 8 (256 <= N <= 2048).
+bool fft_few_waves(int N, long long lines) {
+  return N >= 256 && N <= 2048 && lines * (long long)N < (1LL << 21);
+}
+
 template <int DIR, bool ACCALL>
 hipError_t launch_line_dir(const FftArgs& a, int N, int batch, hipStream_t s) {
   const long long lines = a.lines;
@@ -856,6 +867,19 @@ hipError_t launch_line_dir(const FftArgs& a, int N, int batch, hipStream_t s) {
       case 4: hipLaunchKernelGGL((fft_small_kernel<4, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
       case 8: hipLaunchKernelGGL((fft_small_kernel<8, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
       default: hipLaunchKernelGGL((fft_small_kernel<16, DIR, ACCALL>), grid, dim3(kThreads), 0, s, a); break;
+    }
+    return hipGetLastError();
+  }
+  if (!ACCALL && fft_few_waves(N, lines * batch)) {
+    // 8 elements per thread: twice the threads per line for a pass that would
+    // otherwise leave each CU a handful of waves
+    const int lpb8 = kThreads / (N / 8);
+    const dim3 grid8((unsigned)((lines + lpb8 - 1) / lpb8), (unsigned)batch);
+    switch (N) {
+      case 256: hipLaunchKernelGGL((fft_line_kernel<256, DIR, false, 8>), grid8, dim3(kThreads), 0, s, a); break;
+      case 512: hipLaunchKernelGGL((fft_line_kernel<512, DIR, false, 8>), grid8, dim3(kThreads), 0, s, a); break;
+      case 1024: hipLaunchKernelGGL((fft_line_kernel<1024, DIR, false, 8>), grid8, dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((fft_line_kernel<2048, DIR, false, 8>), grid8, dim3(kThreads), 0, s, a); break;
     }
     return hipGetLastError();
   }
@@ -896,16 +920,25 @@ static hipError_t launch_col_dir(const FftArgs& a, int N, int batch, hipStream_t
   // 4 columns per block where 8 would leave CUs idle (not for the residual
   // epilogue, whose loss partials are counted per 8-column block)
   const bool narrow = a.post != kPostResidual && (a.lines + 7) / 8 * batch < 256;
+  // 8 elements per thread where 16 would leave each CU a handful of waves
+  const bool e8 = fft_few_waves(N, a.lines * batch);
 #define CTV_COLK(NN)                                                                        \
   case NN: {                                                                                \
     constexpr int cb = col_block<NN>();                                                     \
     constexpr int cbn = cb == 8 && NN >= 256 ? 4 : cb;                                      \
+    constexpr int e8ok = NN >= 256 && NN <= 2048;                                           \
     if (narrow && cbn != cb) {                                                              \
       const dim3 grid((unsigned)((a.lines + cbn - 1) / cbn), (unsigned)batch);             \
-      hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cbn>), grid, dim3(cbn * (NN / 16)), 0, s, a); \
+      if (e8ok && e8)                                                                       \
+        hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cbn, e8ok ? 8 : 16>), grid, dim3(cbn * (NN / (e8ok ? 8 : 16))), 0, s, a); \
+      else                                                                                  \
+        hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cbn>), grid, dim3(cbn * (NN / 16)), 0, s, a); \
     } else {                                                                                \
       const dim3 grid((unsigned)((a.lines + cb - 1) / cb), (unsigned)batch);                \
-      hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cb>), grid, dim3(cb * (NN / 16)), 0, s, a); \
+      if (e8ok && e8)                                                                       \
+        hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cb, e8ok ? 8 : 16>), grid, dim3(cb * (NN / (e8ok ? 8 : 16))), 0, s, a); \
+      else                                                                                  \
+        hipLaunchKernelGGL((fft_col_kernel<NN, DIR, cb>), grid, dim3(cb * (NN / 16)), 0, s, a); \
     }                                                                                       \
     break;                                                                                  \
   }
