@@ -30,7 +30,8 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-@pytest.mark.parametrize("shape", [(2, 2), (4, 8), (16, 32), (8, 2), (64, 128), (1024, 1024), (256, 2048), (4096, 8)])
+@pytest.mark.parametrize("shape", [(2, 2), (4, 8), (16, 32), (8, 2), (64, 128), (512, 512), (256, 512), (1024, 1024),
+                                   (256, 2048), (4096, 8)])
 def test_fft2_matches_numpy(shape):
     rng = np.random.default_rng(1)
     x = (rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)).astype(np.complex64)
