@@ -2,6 +2,7 @@
 
     python -m paper_2109_05496_amd.prof_summary stats <kernel_stats.csv> <out.md> --cmd "<command>" [--group G]
     python -m paper_2109_05496_amd.prof_summary pmc <fetch_dir> <write_dir> <valu_dir> <out.md> --cmd "<command>" [--group G]
+    python -m paper_2109_05496_amd.prof_summary counters <dir> <out.md> --cmd "<command>" --group G [--title T]
 
 Both summaries end in a JSON block: per-kernel average durations (stats), or
 per-dispatch FETCH_SIZE / WRITE_SIZE scaled by the factors the same counters
@@ -155,6 +156,43 @@ def pmc(fetch_dir, write_dir, valu_dir, out, cmd, copy_bytes=1 << 30, group="fgp
     open(out, "w").write("\n".join(lines))
 
 
+def counters(d, out, cmd, group, title=None):
+    """Per-dispatch means of every counter of one rocprofv3 --pmc run for the
+    group's kernels, with the wave-time split the SQ counters give: working on
+    an instruction (SQ_ACTIVE_INST_ANY, of which VALU SQ_ACTIVE_INST_VALU),
+    waiting for anything (SQ_WAIT_ANY: waitcnt, barriers) and waiting for an
+    instruction to issue (SQ_WAIT_INST_ANY), as fractions of SQ_WAVE_CYCLES
+    (all in the same 4-cycle units, summed over waves)."""
+    agg = _counters(d)
+    per_kernel = {}
+    for k in sorted(agg):
+        if not k.startswith(GROUPS[group]["kernels"]):
+            continue
+        c = {n: round(_mean(v), 1) for n, v in sorted(agg[k].items())}
+        wc = c.get("SQ_WAVE_CYCLES")
+        split = None
+        if wc:
+            split = {name: round(c[key] / wc, 3) for name, key in
+                     (("issuing", "SQ_ACTIVE_INST_ANY"), ("valu_issuing", "SQ_ACTIVE_INST_VALU"),
+                      ("waiting", "SQ_WAIT_ANY"), ("waiting_to_issue", "SQ_WAIT_INST_ANY")) if key in c}
+        per_kernel[k] = {"dispatches": len(next(iter(agg[k].values()))), "counters": c, "wave_time_split": split}
+    doc = {"group": group, "sources": list(GROUPS[group]["sources"]),
+           "source_sha256": source_hash(GROUPS[group]["sources"]), "kernels": per_kernel}
+    lines = ["# rocprofv3 counter summary" + (f": {title}" if title else ""), "", f"Command: `{cmd}`", "",
+             "Per-dispatch means. The split divides SQ_ACTIVE_INST_ANY (wave-cycles working on an instruction), "
+             "SQ_ACTIVE_INST_VALU (the VALU part), SQ_WAIT_ANY (wave-cycles waiting for anything: waitcnt, "
+             "barriers) and SQ_WAIT_INST_ANY (wave-cycles waiting for an instruction to issue) by "
+             "SQ_WAVE_CYCLES (wave-cycles resident); all in the same units, summed over waves.", "",
+             "| kernel | dispatches | working | VALU working | waiting | waiting to issue |",
+             "|---|---|---|---|---|---|"]
+    for k, v in per_kernel.items():
+        sp = v["wave_time_split"] or {}
+        lines.append(f"| `{k}` | {v['dispatches']} | {sp.get('issuing')} | {sp.get('valu_issuing')} | "
+                     f"{sp.get('waiting')} | {sp.get('waiting_to_issue')} |")
+    lines += _json_block(doc)
+    open(out, "w").write("\n".join(lines))
+
+
 def load_summary(path):
     """The JSON block of a stats or PMC summary, or None if absent or measured
     on other sources than the ones in the tree."""
@@ -196,8 +234,16 @@ if __name__ == "__main__":
     p.add_argument("--group", default="fgp", choices=sorted(GROUPS))
     p.add_argument("--bench-log", default=None, help="output of one of the profiled bench.py runs "
                                                       "(records the launch configuration it used)")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("out")
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--group", required=True, choices=sorted(GROUPS))
+    c.add_argument("--title", default=None)
     a = ap.parse_args()
     if a.what == "stats":
         stats(a.csv, a.out, a.cmd, a.match, a.title, a.group)
+    elif a.what == "counters":
+        counters(a.dir, a.out, a.cmd, a.group, a.title)
     else:
         pmc(a.fetch, a.write, a.valu, a.out, a.cmd, group=a.group, bench_log=a.bench_log)
